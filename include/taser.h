@@ -1,0 +1,157 @@
+/*
+ * taser.h -- C ABI of libtaser.so, a batched TASER detector for AMD MI355X
+ * (gfx950).
+ *
+ * TASER (Triangular Approximate SEmidefinite Relaxation; Castaneda,
+ * Goldstein and Studer, arXiv:1609.01797) detects BPSK/QPSK symbols in
+ * coherent MU-MIMO systems (Section II-A) and jointly estimates the channel
+ * and detects the data in SIMO block-fading systems (Section II-B).  Both
+ * problems become  min over s~ in {-1,+1}^N of s~^T T s~  (eq. (2), eq. (5)),
+ * which Algorithm 1 solves approximately with preconditioned forward-backward
+ * splitting on a lower-triangular factor L~ (Sections III-A to III-D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every data pointer is a DEVICE pointer owned by the caller.  The library
+ *    never allocates, never frees and keeps no per-call state.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Outputs are valid once the stream has reached the call.
+ *  - Argument, shape and support errors are returned synchronously, before
+ *    anything is launched, and then no output is written.  A failed HIP call
+ *    or launch returns TASER_ERR_DEVICE.
+ *  - Numerical conditions never abort: they set per-vector status bits
+ *    (TASER_VEC_*) in an int32 status[V] array.
+ *  - Complex numbers are interleaved float32 pairs (re, im), i.e. the
+ *    memory layout of C99 float complex / numpy complex64.
+ *  - Real vector index s~ = [Re s_1..Re s_U, Im s_1..Im s_U, 1] for QPSK
+ *    and [s_1..s_U, 1] for BPSK (Section II-A); N = 2U+1 or U+1.
+ *  - Lower-triangular matrices are packed row by row:
+ *    element (i, j), j <= i, sits at i*(i+1)/2 + j.
+ *
+ * Readings of the paper that change results (all switchable where noted):
+ *  - The prox of Section III-C normalises each COLUMN k of L~ to norm D_kk.
+ *  - D_kk = sqrt(|T_kk|): the joint-detection T of eq. (5) is negative
+ *    semidefinite, so its diagonal is negative.
+ *  - L~_NN is held at D_NN (the hardware of Section IV-C keeps it constant);
+ *    TASER_FLAG_LITERAL_LAST normalises it like every other column instead.
+ *  - sign(0) = +1 when slicing.
+ *  - A column whose norm is zero or non-finite is reset to D_kk e_k.
+ */
+#ifndef TASER_H
+#define TASER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TASER_ABI_VERSION 1
+#define TASER_MAX_N 129          /* largest problem size N the library accepts */
+
+typedef enum {
+  TASER_OK = 0,
+  TASER_ERR_ARG = -1,            /* null pointer, bad enum, bad alpha / t_max */
+  TASER_ERR_SHAPE = -2,          /* sizes out of range or inconsistent */
+  TASER_ERR_UNSUPPORTED = -3,    /* valid request this build does not implement */
+  TASER_ERR_DEVICE = -5          /* a HIP call or kernel launch failed */
+} taser_status_t;
+
+enum { TASER_BPSK = 1, TASER_QPSK = 2 };
+enum { TASER_COHERENT = 0, TASER_JED = 1 };
+/* Arithmetic of the L~ T~ products in the main loop.  Norms, rsqrt, the
+   preconditioner and the master copy of L~ are float32 in every mode. */
+enum { TASER_PREC_F32 = 0, TASER_PREC_BF16 = 1, TASER_PREC_F16 = 2 };
+enum { TASER_TAU_SPECTRAL = 0,   /* tau = alpha / ||T~||_2 (Algorithm 1 inputs) */
+       TASER_TAU_GIVEN = 1 };    /* tau[v] supplied by the caller */
+
+#define TASER_FLAG_LITERAL_LAST 1 /* normalise column N too (L~_NN = D_NN sign V_NN) */
+
+/* per-vector status bits */
+#define TASER_VEC_DEGENERATE 1   /* some T_kk == 0: no iterations; L~ = D */
+#define TASER_VEC_NONFINITE  2   /* NaN/Inf reached T: no iterations; L~ = D */
+#define TASER_VEC_ZERO_NORM  4   /* a prox column had zero norm and was reset */
+#define TASER_VEC_VNN_NONPOS 8   /* V_NN <= 0 occurred in some iteration */
+
+typedef struct {
+  int32_t num_vectors;  /* V >= 0: received vectors (coherent) or blocks (JED) */
+  int32_t B;            /* receive antennas, >= 1 */
+  int32_t U;            /* coherent: users; JED: K, the data slots after the pilot */
+  int32_t mod;          /* TASER_BPSK or TASER_QPSK */
+  int32_t mode;         /* TASER_COHERENT or TASER_JED */
+  int32_t prec;         /* TASER_PREC_* */
+  int32_t tau_mode;     /* TASER_TAU_* */
+  int32_t y_per_H;      /* coherent: consecutive vectors sharing one H (>= 1,
+                           divides num_vectors); JED: must be 1 */
+  int32_t t_max;        /* iterations, 0 <= t_max <= 100000 */
+  int32_t flags;        /* TASER_FLAG_* */
+  float alpha;          /* 0 < alpha < 1 when tau_mode == TASER_TAU_SPECTRAL */
+} taser_desc_t;
+
+/* Version of this ABI (TASER_ABI_VERSION of the built library). */
+int taser_abi_version(void);
+
+/* Static text for a taser_status_t value. */
+const char* taser_status_string(int status);
+
+/* Problem size N of the real-valued reformulation (Section II): 2U+1 for
+   QPSK, U+1 for BPSK; -1 for an invalid modulation or U < 1. */
+int taser_problem_size(int U, int mod);
+
+/* Host-only validation of a descriptor (no device work): TASER_OK or the
+   error the entry points would return for it. */
+taser_status_t taser_check_desc(const taser_desc_t* desc);
+
+/* Preprocessing: build T (eq. (2) or eq. (5)) and precondition it
+   (Section III-C), then form the step size of Algorithm 1.
+   Inputs
+     coherent: H complex64 [V/y_per_H][B][U] row-major (vector v uses
+               H[v / y_per_H]); y complex64 [V][B]; s0 ignored (may be NULL).
+     JED:      H ignored (may be NULL); y holds Y, complex64 [V][U+1][B]
+               slot-major (y[v][k][b] = antenna b in slot k; slot 0 carries
+               the pilot); s0 complex64 [V], the known first entry s_0 of
+               the paper's s.
+   Outputs (float32)
+     Tt   [V][N][N]  T~ = D^-1 T D^-1, full symmetric matrix
+     D    [V][N]     D_kk = sqrt(|T_kk|)
+     lam  [V]        ||T~||_2 (largest |eigenvalue|, Lanczos in float32)
+     tau  [V]        written with alpha/lam when tau_mode == SPECTRAL;
+                     left untouched (an input of taser_solve) when GIVEN
+     status [V]      TASER_VEC_DEGENERATE / TASER_VEC_NONFINITE or 0 */
+taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void* y,
+                             const void* s0, float* Tt, float* D, float* lam, float* tau,
+                             int32_t* status, void* stream);
+
+/* Algorithm 1, initialisation and main loop (Section III-D):
+   L~(0) = D; t_max times  V = L~ - tril(2 tau L~ T~),  L~ = prox(V).
+   Inputs: Tt [V][N][N], D [V][N], tau [V] (float32), status [V] from
+   taser_build_T (vectors flagged DEGENERATE or NONFINITE run no iterations
+   and get L~ = D).  Output: L [V][N(N+1)/2] packed float32; status gains
+   TASER_VEC_ZERO_NORM / TASER_VEC_VNN_NONPOS bits.  desc->prec selects the
+   product arithmetic (only TASER_PREC_F32 in this entry point). */
+taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
+                           const float* tau, float* L, int32_t* status, void* stream);
+
+/* Algorithm 1 output: sbar_k = sign(L~_{N,k}) for k = 1..N-1 (sign(0) = +1),
+   int8 sbar [V][N-1] in s~ order; margin [V][N-1] float32 = L~_{N,k}/D_kk
+   (the last row of L = L~ D^-1, in [-1, 1]), or NULL. */
+taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const float* D,
+                            int8_t* sbar, float* margin, void* stream);
+
+/* The whole detector in one launch: build T, precondition, step size,
+   t_max iterations and slicing, with T~ and L~ kept on chip.  Same inputs as
+   taser_build_T; tau_in [V] is read when tau_mode == GIVEN (else may be NULL).
+   Outputs: sbar int8 [V][N-1]; margin float32 [V][N-1] or NULL; status [V];
+   L_out [V][N(N+1)/2] float32 or NULL (written only when non-NULL).
+   Supported shapes: N-1 in {16, 32, 64} (other N return
+   TASER_ERR_UNSUPPORTED; use the staged calls). */
+taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
+                         const void* s0, const float* tau_in, int8_t* sbar, float* margin,
+                         int32_t* status, float* L_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TASER_H */

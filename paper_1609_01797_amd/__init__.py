@@ -1,0 +1,220 @@
+"""Batched TASER detection on AMD MI355X: thin Python binding of libtaser.so.
+
+TASER (Castaneda, Goldstein and Studer, arXiv:1609.01797) is a near-ML
+BPSK/QPSK detector for large MU-MIMO systems and a joint channel-estimation
+and detection method for SIMO systems.  All arithmetic runs in the HIP
+kernels of ``libtaser.so``; this module only checks tensor shapes, dtypes and
+devices, allocates outputs with torch (device memory and streams are torch's
+job here), and calls the C ABI declared in ``include/taser.h`` on torch's
+current stream.  If the library is missing every call raises: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
+           "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
+           "TAU_SPECTRAL", "TAU_GIVEN", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtaser.so")
+
+BPSK, QPSK = 1, 2
+COHERENT, JED = 0, 1
+PREC_F32, PREC_BF16, PREC_F16 = 0, 1, 2
+TAU_SPECTRAL, TAU_GIVEN = 0, 1
+FLAG_LITERAL_LAST = 1
+VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS = 1, 2, 4, 8
+
+OK, ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_DEVICE = 0, -1, -2, -3, -5
+
+
+class TaserError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("num_vectors", ctypes.c_int32), ("B", ctypes.c_int32), ("U", ctypes.c_int32),
+                ("mod", ctypes.c_int32), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("tau_mode", ctypes.c_int32), ("y_per_H", ctypes.c_int32),
+                ("t_max", ctypes.c_int32), ("flags", ctypes.c_int32), ("alpha", ctypes.c_float)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load libtaser.so (built by ``python -m paper_1609_01797_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1609_01797_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    D = ctypes.POINTER(Desc)
+    lib.taser_abi_version.restype = ctypes.c_int
+    lib.taser_status_string.restype = ctypes.c_char_p
+    lib.taser_status_string.argtypes = [ctypes.c_int]
+    lib.taser_problem_size.restype = ctypes.c_int
+    lib.taser_problem_size.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.taser_check_desc.restype = ctypes.c_int
+    lib.taser_check_desc.argtypes = [D]
+    lib.taser_build_T.restype = ctypes.c_int
+    lib.taser_build_T.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    lib.taser_solve.restype = ctypes.c_int
+    lib.taser_solve.argtypes = [D, _P, _P, _P, _P, _P, _P]
+    lib.taser_detect.restype = ctypes.c_int
+    lib.taser_detect.argtypes = [D, _P, _P, _P, _P, _P]
+    lib.taser_run.restype = ctypes.c_int
+    lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    _lib = lib
+    return lib
+
+
+def problem_size(U: int, mod: int) -> int:
+    return 2 * U + 1 if mod == QPSK else U + 1
+
+
+def make_desc(V, B, U, mod, mode=COHERENT, prec=PREC_F32, tau_mode=TAU_SPECTRAL, y_per_H=1,
+              t_max=10, flags=0, alpha=0.5) -> Desc:
+    return Desc(int(V), int(B), int(U), int(mod), int(mode), int(prec), int(tau_mode),
+                int(y_per_H), int(t_max), int(flags), float(alpha))
+
+
+def check_desc(desc: Desc) -> int:
+    return load().taser_check_desc(ctypes.byref(desc))
+
+
+def _raise(status: int):
+    if status != OK:
+        raise TaserError(status, load().taser_status_string(status).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _need(t, dtype, numel, name):
+    torch = _torch()
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, numel, name):
+    return None if t is None else _need(t, dtype, numel, name)
+
+
+def _stream(device):
+    return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
+
+
+def _inputs(desc: Desc, H, y, s0):
+    torch = _torch()
+    V, B, U = desc.num_vectors, desc.B, desc.U
+    if desc.mode == COHERENT:
+        ph = _need(H, torch.complex64, (V // max(desc.y_per_H, 1)) * B * U, "H")
+        py = _need(y, torch.complex64, V * B, "y")
+        ps = None
+    else:
+        ph = None
+        py = _need(y, torch.complex64, V * (U + 1) * B, "Y")
+        ps = _need(s0, torch.complex64, V, "s0")
+    return ph, py, ps
+
+
+def build_T(desc: Desc, H, y, s0=None, tau=None):
+    """Preprocessing (Section II, Section III-C): returns dict with Tt [V,N,N],
+    D [V,N], lam [V], tau [V], status [V].  With desc.tau_mode == TAU_GIVEN
+    the given ``tau`` [V] is copied into the result unchanged."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    dev = y.device
+    ph, py, ps = _inputs(desc, H, y, s0)
+    out = {"Tt": torch.empty((V, N, N), dtype=torch.float32, device=dev),
+           "D": torch.empty((V, N), dtype=torch.float32, device=dev),
+           "lam": torch.empty((V,), dtype=torch.float32, device=dev),
+           "tau": torch.empty((V,), dtype=torch.float32, device=dev),
+           "status": torch.empty((V,), dtype=torch.int32, device=dev)}
+    if desc.tau_mode == TAU_GIVEN:
+        _need(tau, torch.float32, V, "tau")
+        out["tau"].copy_(tau)
+    st = lib.taser_build_T(ctypes.byref(desc), ph, py, ps,
+                           *(ctypes.c_void_p(out[k].data_ptr()) for k in ("Tt", "D", "lam", "tau", "status")),
+                           _stream(dev))
+    _raise(st)
+    return out
+
+
+def solve(desc: Desc, Tt, D, tau, status):
+    """Algorithm 1 main loop: returns packed L~ [V, N(N+1)/2]; ``status`` is
+    updated in place."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    P = N * (N + 1) // 2
+    L = torch.empty((V, P), dtype=torch.float32, device=Tt.device)
+    st = lib.taser_solve(ctypes.byref(desc), _need(Tt, torch.float32, V * N * N, "Tt"),
+                         _need(D, torch.float32, V * N, "D"), _need(tau, torch.float32, V, "tau"),
+                         ctypes.c_void_p(L.data_ptr()), _need(status, torch.int32, V, "status"),
+                         _stream(Tt.device))
+    _raise(st)
+    return L
+
+
+def detect(desc: Desc, L, D, want_margin=True):
+    """Algorithm 1 output: returns (sbar int8 [V, N-1], margin float32 [V, N-1] or None)."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    sbar = torch.empty((V, N - 1), dtype=torch.int8, device=L.device)
+    margin = torch.empty((V, N - 1), dtype=torch.float32, device=L.device) if want_margin else None
+    st = lib.taser_detect(ctypes.byref(desc), _need(L, torch.float32, V * N * (N + 1) // 2, "L"),
+                          _need(D, torch.float32, V * N, "D"), ctypes.c_void_p(sbar.data_ptr()),
+                          None if margin is None else ctypes.c_void_p(margin.data_ptr()),
+                          _stream(L.device))
+    _raise(st)
+    return sbar, margin
+
+
+def run(desc: Desc, H, y, s0=None, tau=None, want_margin=False, want_L=False, out=None):
+    """The fused single-launch detector.  Returns dict sbar, status (+ margin,
+    L when requested).  ``out`` may hold preallocated tensors to reuse."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    dev = y.device
+    ph, py, ps = _inputs(desc, H, y, s0)
+    pt = _need(tau, torch.float32, V, "tau") if desc.tau_mode == TAU_GIVEN else None
+    res = out if out is not None else {}
+    if "sbar" not in res:
+        res["sbar"] = torch.empty((V, N - 1), dtype=torch.int8, device=dev)
+        res["status"] = torch.empty((V,), dtype=torch.int32, device=dev)
+    if want_margin and "margin" not in res:
+        res["margin"] = torch.empty((V, N - 1), dtype=torch.float32, device=dev)
+    if want_L and "L" not in res:
+        res["L"] = torch.empty((V, N * (N + 1) // 2), dtype=torch.float32, device=dev)
+    st = lib.taser_run(ctypes.byref(desc), ph, py, ps, pt,
+                       _need(res["sbar"], torch.int8, V * (N - 1), "sbar"),
+                       _opt(res.get("margin") if want_margin else None, torch.float32, V * (N - 1), "margin"),
+                       _need(res["status"], torch.int32, V, "status"),
+                       _opt(res.get("L") if want_L else None, torch.float32, V * N * (N + 1) // 2, "L"),
+                       _stream(dev))
+    _raise(st)
+    return res

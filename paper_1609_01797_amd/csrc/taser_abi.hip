@@ -1,0 +1,141 @@
+// extern "C" entry points of libtaser.so: argument validation and dispatch.
+// Every check happens on the host before any launch; see include/taser.h.
+#include <math.h>
+#include <stdlib.h>
+
+#include "taser_internal.h"
+
+using namespace taser;
+
+namespace {
+
+bool valid_enums(const taser_desc_t* d) {
+  if (d->mod != TASER_BPSK && d->mod != TASER_QPSK) return false;
+  if (d->mode != TASER_COHERENT && d->mode != TASER_JED) return false;
+  if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)
+    return false;
+  if (d->tau_mode != TASER_TAU_SPECTRAL && d->tau_mode != TASER_TAU_GIVEN) return false;
+  if (d->flags & ~TASER_FLAG_LITERAL_LAST) return false;
+  return true;
+}
+
+taser_status_t check(const taser_desc_t* d) {
+  if (!d) return TASER_ERR_ARG;
+  if (!valid_enums(d)) return TASER_ERR_ARG;
+  if (d->t_max < 0 || d->t_max > 100000) return TASER_ERR_ARG;
+  if (d->tau_mode == TASER_TAU_SPECTRAL && !(d->alpha > 0.f && d->alpha < 1.f)) return TASER_ERR_ARG;
+  if (d->num_vectors < 0 || d->B < 1 || d->U < 1) return TASER_ERR_SHAPE;
+  const int N = taser_problem_size(d->U, d->mod);
+  if (N < 2 || N > TASER_MAX_N) return TASER_ERR_SHAPE;
+  if (d->y_per_H < 1) return TASER_ERR_SHAPE;
+  if (d->mode == TASER_JED && d->y_per_H != 1) return TASER_ERR_SHAPE;
+  if (d->num_vectors % d->y_per_H != 0) return TASER_ERR_SHAPE;
+  return TASER_OK;
+}
+
+StagedArgs staged_args(const taser_desc_t* d) {
+  StagedArgs a{};
+  a.V = d->num_vectors; a.B = d->B; a.U = d->U; a.N = taser_problem_size(d->U, d->mod);
+  a.mod = d->mod; a.mode = d->mode; a.y_per_H = d->y_per_H; a.t_max = d->t_max;
+  a.flags = d->flags; a.tau_mode = d->tau_mode; a.alpha = d->alpha;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int taser_abi_version(void) { return TASER_ABI_VERSION; }
+
+const char* taser_status_string(int status) {
+  switch (status) {
+    case TASER_OK: return "TASER_OK";
+    case TASER_ERR_ARG: return "TASER_ERR_ARG: invalid argument (null pointer, enum, alpha or t_max)";
+    case TASER_ERR_SHAPE: return "TASER_ERR_SHAPE: sizes out of range or inconsistent";
+    case TASER_ERR_UNSUPPORTED: return "TASER_ERR_UNSUPPORTED: request not implemented for this shape or precision";
+    case TASER_ERR_DEVICE: return "TASER_ERR_DEVICE: a HIP call or kernel launch failed";
+    default: return "TASER: unknown status";
+  }
+}
+
+int taser_problem_size(int U, int mod) {
+  if (U < 1) return -1;
+  if (mod == TASER_QPSK) return 2 * U + 1;
+  if (mod == TASER_BPSK) return U + 1;
+  return -1;
+}
+
+taser_status_t taser_check_desc(const taser_desc_t* desc) { return check(desc); }
+
+taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void* y,
+                             const void* s0, float* Tt, float* D, float* lam, float* tau,
+                             int32_t* status, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  StagedArgs a = staged_args(desc);
+  if (a.V == 0) return TASER_OK;
+  const bool jed = desc->mode == TASER_JED;
+  if (!y || !Tt || !D || !lam || !tau || !status) return TASER_ERR_ARG;
+  if (!jed && !H) return TASER_ERR_ARG;
+  if (jed && !s0) return TASER_ERR_ARG;
+  if (build_T_lds_bytes(a.B, a.U, a.N) == 0) return TASER_ERR_UNSUPPORTED;
+  a.H = static_cast<const float2*>(H);
+  a.y = static_cast<const float2*>(y);
+  a.s0 = static_cast<const float2*>(s0);
+  a.Tt = Tt; a.D = D; a.lam = lam; a.tau = tau; a.status = status;
+  return launch_build_T(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
+                                                                          : TASER_ERR_DEVICE;
+}
+
+taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
+                           const float* tau, float* L, int32_t* status, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  if (desc->prec != TASER_PREC_F32) return TASER_ERR_UNSUPPORTED;
+  StagedArgs a = staged_args(desc);
+  if (a.V == 0) return TASER_OK;
+  if (!Tt || !D || !tau || !L || !status) return TASER_ERR_ARG;
+  return launch_solve(a, Tt, D, tau, L, status, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
+taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const float* D,
+                            int8_t* sbar, float* margin, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  const int N = taser_problem_size(desc->U, desc->mod);
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!L || !D || !sbar) return TASER_ERR_ARG;
+  return launch_detect(desc->num_vectors, N, L, D, sbar, margin,
+                       static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
+taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y, const void* s0,
+                         const float* tau_in, int8_t* sbar, float* margin, int32_t* status,
+                         float* L_out, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  FusedArgs a{};
+  a.V = desc->num_vectors; a.B = desc->B; a.U = desc->U;
+  a.N = taser_problem_size(desc->U, desc->mod);
+  a.mod = desc->mod; a.mode = desc->mode; a.y_per_H = desc->y_per_H; a.t_max = desc->t_max;
+  a.flags = desc->flags; a.tau_mode = desc->tau_mode; a.prec = desc->prec; a.alpha = desc->alpha;
+  if (!fused_supported(a)) return TASER_ERR_UNSUPPORTED;
+  if (a.V == 0) return TASER_OK;
+  const bool jed = desc->mode == TASER_JED;
+  if (!y || !sbar || !status) return TASER_ERR_ARG;
+  if (!jed && !H) return TASER_ERR_ARG;
+  if (jed && !s0) return TASER_ERR_ARG;
+  if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
+  a.H = static_cast<const float2*>(H);
+  a.y = static_cast<const float2*>(y);
+  a.s0 = static_cast<const float2*>(s0);
+  a.tau_in = tau_in; a.sbar = sbar; a.margin = margin; a.status = status; a.L_out = L_out;
+  return launch_fused(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
+                                                                        : TASER_ERR_DEVICE;
+}
+
+}  // extern "C"

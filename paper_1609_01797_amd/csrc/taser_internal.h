@@ -1,0 +1,54 @@
+// Internal declarations shared by the HIP translation units of libtaser.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/taser.h"
+
+namespace taser {
+
+constexpr int kWave = 64;
+
+// Flat argument block for the staged kernels (plain pointers and sizes).
+struct StagedArgs {
+  int32_t V, B, U, N, mod, mode, y_per_H, t_max, flags, tau_mode;
+  float alpha;
+  const float2* H;     // coherent channel matrices
+  const float2* y;     // coherent receive vectors, or JED blocks Y
+  const float2* s0;    // JED pilots
+  float* Tt;           // [V][N][N]
+  float* D;            // [V][N]
+  float* lam;          // [V]
+  float* tau;          // [V]
+  int32_t* status;     // [V]
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_build_T(const StagedArgs& a, hipStream_t s);
+hipError_t launch_solve(const StagedArgs& a, const float* Tt, const float* D, const float* tau,
+                        float* L, int32_t* status, hipStream_t s);
+hipError_t launch_detect(int32_t V, int32_t N, const float* L, const float* D, int8_t* sbar,
+                         float* margin, hipStream_t s);
+
+// Fused single-launch detector for N-1 in {16, 32, 64}.
+struct FusedArgs {
+  int32_t V, B, U, N, mod, mode, y_per_H, t_max, flags, tau_mode, prec;
+  float alpha;
+  const float2* H;
+  const float2* y;
+  const float2* s0;
+  const float* tau_in;
+  int8_t* sbar;
+  float* margin;
+  int32_t* status;
+  float* L_out;
+};
+bool fused_supported(const FusedArgs& a);
+hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
+
+// LDS bytes the staged build kernel needs (0 if the shape does not fit).
+size_t build_T_lds_bytes(int B, int U, int N);
+size_t solve_lds_bytes(int N);
+
+}  // namespace taser

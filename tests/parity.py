@@ -1,0 +1,38 @@
+"""Helpers shared by the GPU parity tests (no detector arithmetic here)."""
+import numpy as np
+
+# Tolerances: float32 path vs the float64 oracle (per-vector relative
+# Frobenius error of L~) and the margin below which a decision may differ.
+L_REL_TOL = 1e-5
+MARGIN_TOL = 1e-4
+
+
+def unpack_lower(Lp, N):
+    """[V, N(N+1)/2] packed rows -> [V, N, N] lower triangular."""
+    Lp = np.asarray(Lp, dtype=np.float64)
+    V = Lp.shape[0]
+    out = np.zeros((V, N, N))
+    r, c = np.tril_indices(N)
+    out[:, r, c] = Lp
+    return out
+
+
+def rel_frobenius(L_gpu, L_ref):
+    num = np.linalg.norm((L_gpu - L_ref).reshape(L_ref.shape[0], -1), axis=1)
+    den = np.linalg.norm(L_ref.reshape(L_ref.shape[0], -1), axis=1)
+    return num / den
+
+
+def assert_L_parity(L_gpu, L_ref, tol=L_REL_TOL):
+    err = rel_frobenius(L_gpu, L_ref)
+    worst = int(np.argmax(err))
+    assert err.max() <= tol, f"max rel err {err.max():.3e} at vector {worst} (p99.9 {np.quantile(err, 0.999):.3e})"
+    return err
+
+
+def assert_decisions(sbar_gpu, sbar_ref, margin_ref, tol=MARGIN_TOL):
+    sbar_gpu = np.asarray(sbar_gpu)
+    diff = sbar_gpu != sbar_ref
+    bad = diff & (np.abs(margin_ref) >= tol)
+    assert not bad.any(), f"{int(bad.sum())} decisions differ with |margin| >= {tol}"
+    return int(diff.sum())

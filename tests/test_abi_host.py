@@ -1,0 +1,100 @@
+"""Host-only checks of libtaser.so: it loads, exports every declared symbol
+and rejects bad arguments synchronously (no device work is started)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1609_01797_amd as taser
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "taser.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(taser_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = taser.load()
+    names = declared_functions()
+    assert "taser_build_T" in names and "taser_solve" in names and "taser_detect" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_sizes():
+    lib = taser.load()
+    assert lib.taser_abi_version() == 1
+    assert lib.taser_problem_size(16, taser.QPSK) == 33
+    assert lib.taser_problem_size(32, taser.BPSK) == 33
+    assert lib.taser_problem_size(0, taser.QPSK) == -1
+    assert lib.taser_problem_size(4, 7) == -1
+    assert b"TASER_ERR_SHAPE" in lib.taser_status_string(taser.ERR_SHAPE)
+
+
+def _d(**kw):
+    base = dict(V=64, B=32, U=8, mod=taser.QPSK)
+    base.update(kw)
+    return taser.make_desc(**base)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(), taser.OK),
+    (dict(mod=3), taser.ERR_ARG),
+    (dict(mode=2), taser.ERR_ARG),
+    (dict(prec=9), taser.ERR_ARG),
+    (dict(tau_mode=2), taser.ERR_ARG),
+    (dict(flags=2), taser.ERR_ARG),
+    (dict(t_max=-1), taser.ERR_ARG),
+    (dict(alpha=0.0), taser.ERR_ARG),
+    (dict(alpha=1.0), taser.ERR_ARG),
+    (dict(alpha=float("nan")), taser.ERR_ARG),
+    (dict(alpha=2.0, tau_mode=taser.TAU_GIVEN), taser.OK),
+    (dict(V=-1), taser.ERR_SHAPE),
+    (dict(B=0), taser.ERR_SHAPE),
+    (dict(U=0), taser.ERR_SHAPE),
+    (dict(U=65), taser.ERR_SHAPE),          # N = 131 > TASER_MAX_N
+    (dict(U=64), taser.OK),                 # N = 129
+    (dict(y_per_H=0), taser.ERR_SHAPE),
+    (dict(y_per_H=5), taser.ERR_SHAPE),     # does not divide V
+    (dict(y_per_H=16), taser.OK),
+    (dict(mode=taser.JED, y_per_H=2), taser.ERR_SHAPE),
+])
+def test_check_desc(kw, expect):
+    assert taser.check_desc(_d(**kw)) == expect
+
+
+def test_entry_points_reject_before_any_launch():
+    lib = taser.load()
+    bad = _d(mod=5)
+    z = ctypes.c_void_p(0)
+    assert lib.taser_build_T(ctypes.byref(bad), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_solve(ctypes.byref(bad), z, z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_detect(ctypes.byref(bad), z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_run(ctypes.byref(bad), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
+    good = _d()
+    # valid descriptor, null buffers: rejected synchronously
+    assert lib.taser_build_T(ctypes.byref(good), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_solve(ctypes.byref(good), z, z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_detect(ctypes.byref(good), z, z, z, z, z) == taser.ERR_ARG
+    # nothing to do: OK without touching the device
+    empty = _d(V=0)
+    assert lib.taser_build_T(ctypes.byref(empty), z, z, z, z, z, z, z, z, z) == taser.OK
+    assert lib.taser_solve(ctypes.byref(empty), z, z, z, z, z, z) == taser.OK
+    assert lib.taser_detect(ctypes.byref(empty), z, z, z, z, z) == taser.OK
+    # bf16 products are not offered by the staged solve
+    assert lib.taser_solve(ctypes.byref(_d(prec=taser.PREC_BF16)), z, z, z, z, z, z) == taser.ERR_UNSUPPORTED
+    # a channel too large for the staged build's LDS copy
+    assert lib.taser_build_T(ctypes.byref(_d(B=4096, U=16)), z, z, z, z, z, z, z, z, z) in (taser.ERR_ARG, taser.ERR_UNSUPPORTED)
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    d = _d(V=2, B=4, U=2)
+    H = torch.zeros((2, 4, 2), dtype=torch.complex64)
+    y = torch.zeros((2, 4), dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        taser.build_T(d, H, y)
