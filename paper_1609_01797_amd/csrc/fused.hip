@@ -1,10 +1,483 @@
-// Fused single-launch TASER (placeholder until the MFMA kernel lands).
+// Fused single-launch TASER for groups of 16 received vectors that share
+// one channel matrix H (coherent QPSK, U = 16 users, N = 33).
+//
+// One wave detects one group.  The 16 vectors are the N dimension of
+// 16x16x4 float32 MFMAs, so the preconditioned Gram block G~ (the 32x32
+// upper-left block of T~, identical for the 16 vectors) is the shared A
+// operand and stays in 16 VGPRs for the whole solve.  T~ is bordered:
+//     T~ = [ G~    c~_v ]      L~ = [ L11   0   ]
+//          [ c~_v^T  1  ]           [ l21^T l22 ]
+// Row i of V = L~ - tril(2 tau L~ T~) depends on row i of L~ only
+// (Algorithm 1, line 4), so the rows are processed one after another in
+// registers.  Register layout: lane l serves vector n = l % 16 and column
+// quad g = l / 16; for a row of L~ it holds columns 16 mt + 4 r + g
+// (mt in {0,1}, r in 0..3) in register (mt, r).  With the MFMA output rows
+// permuted by jj(m) = 4 (m % 4) + m / 4, the product's output registers are
+// exactly the next iteration's B operands, and each K-step covers four
+// consecutive columns, so the triangular structure skips whole K-steps.
+// Column norms (the prox of Section III-C) are then sums inside a lane.
+#include <math.h>
+
+#include <type_traits>
+
 #include "taser_internal.h"
 
 namespace taser {
+namespace {
 
-bool fused_supported(const FusedArgs&) { return false; }
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-hipError_t launch_fused(const FusedArgs&, hipStream_t) { return hipErrorNotSupported; }
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (Begin < End) {
+    f(std::integral_constant<int, Begin>{});
+    sfor<Begin + 1, End>(f);
+  }
+}
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Sum over the four lanes that serve one vector (lanes n, n+16, n+32, n+48).
+__device__ __forceinline__ float sum_groups(float x) {
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+constexpr int kLanczosSteps = 14;  // Krylov dimension for ||T~||_2
+constexpr int kLaguerreIters = 12;
+
+// Largest eigenvalue of the symmetric tridiagonal (al, b2 = beta^2) of size M
+// by Laguerre's method from the Gershgorin upper bound.  The characteristic
+// polynomial has only real roots, so from the right the iteration decreases
+// monotonically to the largest root (cubic convergence).  The ratios
+// d_k = p_k / p_{k-1} of the leading principal minors of (x I - T) give
+// G = p'/p and H = -(p'/p)'.
+template <int M>
+__device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (&b2)[M]) {
+  float x = -3.4e38f;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const float rad = (k > 0 ? sqrtf(b2[k - 1]) : 0.f) + (k < M - 1 ? sqrtf(b2[k]) : 0.f);
+    x = fmaxf(x, al[k] + rad);
+  }
+  x = x * (1.f + 1e-6f) + 1e-30f;
+  for (int it = 0; it < kLaguerreIters; ++it) {
+    float d = x - al[0];
+    float e = 1.f, f = 0.f;
+    float id = 1.f / d;
+    float G = e * id, Hs = G * G;
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+      const float dn = (x - al[k]) - b2[k - 1] * id;
+      const float en = 1.f + b2[k - 1] * e * id * id;
+      const float fn = b2[k - 1] * id * id * (f - 2.f * e * e * id);
+      d = dn; e = en; f = fn;
+      id = 1.f / d;
+      const float r = e * id;
+      G += r;
+      Hs += r * r - f * id;
+    }
+    const float disc = fmaxf(0.f, (float)(M - 1) * ((float)M * Hs - G * G));
+    const float step = (float)M / (G + sqrtf(disc));
+    if (!(step > 0.f) || !isfinite(step)) break;
+    x -= step;
+    if (step <= 1e-7f * x) break;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
+  __shared__ float2 Gs[16 * 16];   // G = H^H H, [row][col]
+  __shared__ float2 bs[16 * 16];   // b = H^H y, [user][vector]
+  __shared__ float yy2[16];        // ||y||^2 per vector
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15;         // vector within the group (MFMA N index)
+  const int g = lane >> 4;         // column quad (MFMA K / output row group)
+  const long long v0 = (long long)blockIdx.x * 16;
+  const long long v = v0 + n;
+  const int B = a.B;
+  const float2* Hg = a.H + (v0 / a.y_per_H) * (long long)B * 16;
+  const float2* yv = a.y + v * B;
+
+  // ---------------- preprocessing: G = H^H H, b = H^H y on MFMA ----------------
+  f4 reG = {0.f, 0.f, 0.f, 0.f}, imG = reG, reb = reG, imb = reG;
+  float ysq = 0.f;
+  for (int r0 = 0; r0 < B; r0 += 4) {
+    const int row = r0 + g;
+    const float2 h = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
+    const float2 y = row < B ? yv[row] : make_float2(0.f, 0.f);
+    reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
+    reG = mfma(h.y, h.y, reG);
+    imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
+    imG = mfma(h.y, -h.x, imG);
+    reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
+    reb = mfma(h.y, y.y, reb);
+    imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
+    imb = mfma(h.y, -y.x, imb);
+    ysq += y.x * y.x + y.y * y.y;
+  }
+  ysq = sum_groups(ysq);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    Gs[(4 * g + r) * 16 + n] = make_float2(reG[r], imG[r]);
+    bs[(4 * g + r) * 16 + n] = make_float2(reb[r], imb[r]);
+  }
+  if (g == 0) yy2[n] = ysq;
+  __syncthreads();
+
+  // ---------------- Jacobi preconditioning (Section III-C) ----------------
+  bool bad_group = false, deg_group = false, bad_vec = false, deg_vec = false;
+  auto Du = [&](int u) {
+    const float d = fabsf(Gs[u * 17].x);
+    return d == 0.f ? 1.f : sqrtf(d);
+  };
+  const float yn = yy2[n];
+  deg_vec = yn == 0.f;
+  bad_vec = !isfinite(yn);
+  const float DN = (yn == 0.f || !isfinite(yn)) ? 1.f : sqrtf(yn);
+
+  // A operands: A[mt][kt][s] = G~[16 mt + jj(n)][16 kt + 4 s + g]
+  float A[2][2][4];
+  {
+    const int aa = 4 * (n & 3) + (n >> 2);
+    const float da = Du(aa);
+    if (Gs[aa * 17].x == 0.f) deg_group = true;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int bb = 4 * s + g;
+      const float2 gab = Gs[aa * 16 + bb];
+      if (!isfinite(gab.x) || !isfinite(gab.y)) bad_group = true;
+      const float inv = 1.f / (da * Du(bb));
+      A[0][0][s] = gab.x * inv;
+      A[0][1][s] = -gab.y * inv;
+      A[1][0][s] = gab.y * inv;
+      A[1][1][s] = gab.x * inv;
+    }
+  }
+  // per-lane column data: columns j = 16 mt + 4 r + g, user u = 4 r + g
+  float Dc[4], ct[2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int u = 4 * r + g;
+    Dc[r] = Du(u);
+    const float2 bu = bs[u * 16 + n];
+    if (!isfinite(bu.x) || !isfinite(bu.y)) bad_vec = true;
+    const float inv = 1.f / (Dc[r] * DN);
+    ct[0][r] = -bu.x * inv;          // last column of T: -Hbar^T ybar
+    ct[1][r] = -bu.y * inv;
+  }
+  // group-wide and per-vector flags
+  const unsigned long long mg = __ballot(bad_group) | 0ull;
+  const unsigned long long md = __ballot(deg_group) | 0ull;
+  const unsigned long long mbv = __ballot(bad_vec);
+  const unsigned long long mdv = __ballot(deg_vec);
+  auto fold = [&](unsigned long long m) {
+    return (unsigned)((m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xFFFFull);
+  };
+  const bool nonfinite = mg != 0ull || ((fold(mbv) >> n) & 1u);
+  const bool degenerate = !nonfinite && (md != 0ull || ((fold(mdv) >> n) & 1u));
+  const bool skip = nonfinite || degenerate;
+  if (skip) {
+    // keep the arithmetic of the other vectors clean; this vector's results
+    // are replaced at the end
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { ct[0][r] = 0.f; ct[1][r] = 0.f; }
+  }
+  if (mg != 0ull) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) A[mt][kt][s] = 0.f;
+  }
+
+  // ---------------- step size tau = alpha / ||T~||_2 ----------------
+  float tau;
+  if (a.tau_mode == TASER_TAU_GIVEN) {
+    tau = a.tau_in[v];
+  } else {
+    // Lanczos from T~ e_N = [c~; 1] (a good start: the dominant eigenvector of
+    // T~ weighs the last coordinate heavily), plain three-term recurrence.
+    float al[kLanczosSteps], b2[kLanczosSteps];
+    float Q[2][4], Qp[2][4], q32, qp32 = 0.f, beta = 0.f;
+    float nrm = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { Q[mt][r] = ct[mt][r]; Qp[mt][r] = 0.f; nrm += Q[mt][r] * Q[mt][r]; }
+    nrm = sum_groups(nrm) + 1.f;
+    const float inv0 = 1.f / sqrtf(nrm);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Q[mt][r] *= inv0;
+    q32 = inv0;
+    bool done = false;
+    float scale = 0.f;
+    sfor<0, kLanczosSteps>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      f4 acc[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[mt] = mfma(A[mt][kt][s], Q[kt][s], acc[mt]);
+      }
+      float W[2][4];
+      float cq = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          W[mt][r] = acc[mt][r] + ct[mt][r] * q32;
+          cq += ct[mt][r] * Q[mt][r];
+        }
+      float w32 = sum_groups(cq) + q32;
+      float dot = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dot += W[mt][r] * Q[mt][r];
+      const float alj = sum_groups(dot) + w32 * q32;
+      float ww = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          W[mt][r] -= alj * Q[mt][r] + beta * Qp[mt][r];
+          ww += W[mt][r] * W[mt][r];
+        }
+      w32 -= alj * q32 + beta * qp32;
+      const float bb = sum_groups(ww) + w32 * w32;
+      // After a breakdown (an invariant Krylov subspace) the remaining
+      // diagonal entries are parked far below the spectrum and decoupled.
+      if (!done) {
+        al[j] = alj;
+        b2[j] = bb;
+        scale = fmaxf(scale, fabsf(alj));
+        if (!(bb > 1e-12f * scale * scale)) { done = true; b2[j] = 0.f; }
+      } else {
+        al[j] = -1e30f;
+        b2[j] = 0.f;
+      }
+      beta = sqrtf(bb);
+      const float ib = beta > 0.f ? 1.f / beta : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { Qp[mt][r] = Q[mt][r]; Q[mt][r] = W[mt][r] * ib; }
+      qp32 = q32;
+      q32 = w32 * ib;
+    });
+    const float lam = tridiag_top<kLanczosSteps>(al, b2);
+    tau = a.alpha / (lam > 0.f ? lam : 1.f);
+  }
+  const float m2tau = -2.f * tau;
+
+  // ---------------- Algorithm 1: L~(0) = D, t_max FBS steps ----------------
+  // Lr[i][mt][r] is stored only where 16 mt + 4 r <= i (otherwise the whole
+  // register is in the strictly upper triangle for every lane).
+  float Lr[32][2][4];
+  float l21[2][4];
+  float l22 = DN;
+  sfor<0, 32>([&](auto ic) {
+    constexpr int I = decltype(ic)::value;
+    sfor<0, 2>([&](auto mc) {
+      constexpr int MT = decltype(mc)::value;
+      sfor<0, 4>([&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        if constexpr (16 * MT + 4 * R <= I) {
+          const int j = 16 * MT + 4 * R + g;
+          Lr[I][MT][R] = (j == I) ? Dc[R] : 0.f;
+        }
+      });
+    });
+  });
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) l21[mt][r] = 0.f;
+
+  const bool pin = !(a.flags & TASER_FLAG_LITERAL_LAST);
+  int st_bits = 0;
+  const int iters = a.t_max;
+  for (int t = 0; t < iters; ++t) {
+    float nsq[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nsq[mt][r] = 0.f;
+
+    // rows 0..31: V = L~ - 2 tau tril(L~ T~), restricted to the G~ block
+    sfor<0, 32>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      f4 acc[2];
+      sfor<0, 2>([&](auto mc) {
+        constexpr int MT = decltype(mc)::value;
+        if constexpr (16 * MT <= I) {
+          acc[MT] = f4{0.f, 0.f, 0.f, 0.f};
+          sfor<0, 2>([&](auto kc) {
+            constexpr int KT = decltype(kc)::value;
+            sfor<0, 4>([&](auto sc) {
+              constexpr int S = decltype(sc)::value;
+              if constexpr (16 * KT + 4 * S <= I)
+                acc[MT] = mfma(A[MT][KT][S], Lr[I][KT][S], acc[MT]);
+            });
+          });
+        }
+      });
+      sfor<0, 2>([&](auto mc) {
+        constexpr int MT = decltype(mc)::value;
+        sfor<0, 4>([&](auto rc) {
+          constexpr int R = decltype(rc)::value;
+          if constexpr (16 * MT + 4 * R <= I) {
+            float x = fmaf(m2tau, acc[MT][R], Lr[I][MT][R]);
+            if constexpr (16 * MT + 4 * R + 3 > I) {
+              if (g > I - 16 * MT - 4 * R) x = 0.f;   // strictly upper part
+            }
+            Lr[I][MT][R] = x;
+            nsq[MT][R] = fmaf(x, x, nsq[MT][R]);
+          }
+        });
+      });
+    });
+
+    // last row: l21^T G~ + l22 c~^T, and V_NN
+    float cl = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cl += l21[mt][r] * ct[mt][r];
+    cl = sum_groups(cl);
+    {
+      f4 acc[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc[mt] = mfma(A[mt][kt][s], l21[kt][s], acc[mt]);
+      }
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float x = fmaf(m2tau, fmaf(l22, ct[mt][r], acc[mt][r]), l21[mt][r]);
+          l21[mt][r] = x;
+          nsq[mt][r] = fmaf(x, x, nsq[mt][r]);
+        }
+    }
+    const float vnn = fmaf(m2tau, cl + l22, l22);   // T~_NN = 1
+    if (!(vnn > 0.f)) st_bits |= TASER_VEC_VNN_NONPOS;
+
+    // prox: column j <- D_j V_:,j / ||V_:,j||
+    float sc[2][4];
+    bool any_bad = false;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float q = nsq[mt][r];
+        const bool ok = q > 0.f && q < 3.4e38f;
+        sc[mt][r] = ok ? Dc[r] * __builtin_amdgcn_rsqf(q) : 0.f;
+        any_bad |= !ok;
+      }
+    sfor<0, 32>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      sfor<0, 2>([&](auto mc) {
+        constexpr int MT = decltype(mc)::value;
+        sfor<0, 4>([&](auto rc) {
+          constexpr int R = decltype(rc)::value;
+          if constexpr (16 * MT + 4 * R <= I) Lr[I][MT][R] *= sc[MT][R];
+        });
+      });
+    });
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) l21[mt][r] *= sc[mt][r];
+    if (__builtin_expect(__ballot(any_bad) != 0ull, 0)) {
+      // reset columns with zero / non-finite norm to D_jj e_j
+      if (any_bad) st_bits |= TASER_VEC_ZERO_NORM;
+      sfor<0, 32>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int MT = I / 16, R = (I % 16) / 4;
+        if (sc[MT][R] == 0.f && g == (I & 3)) Lr[I][MT][R] = Dc[R];
+      });
+    }
+    if (pin) {
+      l22 = DN;
+    } else if (vnn != 0.f && isfinite(vnn)) {
+      l22 = vnn > 0.f ? DN : -DN;
+    } else {
+      l22 = DN;
+      st_bits |= TASER_VEC_ZERO_NORM;
+    }
+  }
+
+  // ---------------- slicing and outputs ----------------
+  int bits = st_bits;
+  bits |= __shfl_xor(bits, 16, 64);
+  bits |= __shfl_xor(bits, 32, 64);
+  if (skip) bits = nonfinite ? TASER_VEC_NONFINITE : TASER_VEC_DEGENERATE;
+
+  int8_t* sb = a.sbar + v * 32;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * mt + 4 * r + g;
+      const float x = skip ? 0.f : l21[mt][r];
+      sb[j] = x >= 0.f ? (int8_t)1 : (int8_t)-1;
+      if (a.margin) a.margin[v * 32 + j] = skip ? 0.f : x / Dc[r];
+    }
+  if (g == 0) a.status[v] = bits;
+  if (a.L_out) {
+    float* Lo = a.L_out + v * 561;
+    sfor<0, 32>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      sfor<0, 2>([&](auto mc) {
+        constexpr int MT = decltype(mc)::value;
+        sfor<0, 4>([&](auto rc) {
+          constexpr int R = decltype(rc)::value;
+          if constexpr (16 * MT + 4 * R <= I) {
+            const int j = 16 * MT + 4 * R + g;
+            if (j <= I) {
+              float x = Lr[I][MT][R];
+              if (skip) x = (j == I) ? (nonfinite ? 1.f : Dc[R]) : 0.f;
+              Lo[I * (I + 1) / 2 + j] = x;
+            }
+          }
+        });
+      });
+    });
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Lo[528 + 16 * mt + 4 * r + g] = skip ? 0.f : l21[mt][r];
+    if (g == 0) Lo[560] = skip ? (nonfinite ? 1.f : DN) : l22;
+  }
+}
+
+}  // namespace
+
+bool fused_supported(const FusedArgs& a) {
+  return a.mode == TASER_COHERENT && a.mod == TASER_QPSK && a.U == 16 && a.prec == TASER_PREC_F32 &&
+         a.y_per_H % 16 == 0 && a.B >= 1;
+}
+
+hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
+  const int groups = a.V / 16;
+  hipLaunchKernelGGL(fused_group_qpsk16, dim3(groups), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
 
 }  // namespace taser

@@ -1,0 +1,115 @@
+"""Parity of the fused single-launch path (taser_run) against the FP64 oracle,
+through the C ABI: a slice of the 128x16 QPSK batched workload, the full
+65,536-vector batch in the launch configuration the benchmark times (checked
+on a sample the oracle computes), degenerate groups and ragged sizes."""
+import numpy as np
+import pytest
+
+import oracle
+import sim
+from parity import assert_L_parity, assert_decisions, unpack_lower
+
+pytestmark = pytest.mark.gpu
+
+B, U, N, YPH = 128, 16, 33, 16
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def fused(taser, desc, H, y, tau=None, want_L=True):
+    import torch
+    res = taser.run(desc, _cuda(H), _cuda(y), tau=None if tau is None else _cuda(tau),
+                    want_margin=True, want_L=want_L)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+def _group_oracle(d, alpha, t_max, tau=None, idx=None, pin_last=True):
+    Hv = np.repeat(d["H"], d["y_per_H"], axis=0)
+    y = d["y"]
+    if idx is not None:
+        Hv, y = Hv[idx], y[idx]
+    return oracle.detect_coherent(Hv, y, oracle.QPSK, alpha=alpha, t_max=t_max, tau=tau, pin_last=pin_last)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.9])
+def test_fused_slice_given_tau(gpu_lib, alpha):
+    d = sim.gen_mimo(B, U, oracle.QPSK, 64, YPH, 10.0, sim.seed_for(2, shard=1))
+    ref = _group_oracle(d, alpha, 10)
+    desc = gpu_lib.make_desc(1024, B, U, oracle.QPSK, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=YPH, t_max=10)
+    g = fused(gpu_lib, desc, d["H"], d["y"], tau=ref["tau"].astype(np.float32))
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+    np.testing.assert_array_equal(g["status"], ref["status"])
+    np.testing.assert_allclose(g["margin"], ref["margin"], atol=2e-5)
+
+
+@pytest.mark.parametrize("snr", [0.0, 10.0, 20.0])
+def test_fused_slice_spectral(gpu_lib, snr):
+    """tau from the in-kernel Lanczos + Laguerre estimate of ||T~||_2."""
+    d = sim.gen_mimo(B, U, oracle.QPSK, 64, YPH, snr, sim.seed_for(2, snr_index=int(snr), shard=2))
+    ref = _group_oracle(d, 0.5, 10)
+    desc = gpu_lib.make_desc(1024, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=0.5)
+    g = fused(gpu_lib, desc, d["H"], d["y"])
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
+def test_fused_full_batch_bench_configuration(gpu_lib):
+    """The benchmark's launch: 4,096 channels x 16 vectors, tau spectral,
+    t_max = 10, no L output.  Decisions are checked on a random sample of
+    2,048 vectors against the oracle; L~ on the same sample from a second
+    launch that also writes L~."""
+    d = sim.gen_mimo(B, U, oracle.QPSK, 4096, YPH, 10.0, sim.seed_for(2, snr_index=5))
+    V = 4096 * YPH
+    desc = gpu_lib.make_desc(V, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=0.5)
+    g = fused(gpu_lib, desc, d["H"], d["y"], want_L=False)
+    idx = np.sort(np.random.default_rng(7).choice(V, size=2048, replace=False))
+    ref = _group_oracle(d, 0.5, 10, idx=idx)
+    assert_decisions(g["sbar"][idx], ref["sbar"], ref["margin"])
+    assert np.all(g["status"] == 0)
+    g2 = fused(gpu_lib, desc, d["H"], d["y"], want_L=True)
+    np.testing.assert_array_equal(g2["sbar"], g["sbar"])
+    assert_L_parity(unpack_lower(g2["L"][idx], N), ref["L"])
+
+
+def test_fused_degenerate_groups(gpu_lib):
+    d = sim.gen_mimo(B, U, oracle.QPSK, 4, YPH, 5.0, 4242)
+    H, y = d["H"].copy(), d["y"].copy()
+    H[1, :, 3] = 0            # group 1: zero channel column -> every vector degenerate
+    y[2 * 16 + 5] = 0         # group 2, vector 5: y = 0
+    y[2 * 16 + 9, 7] = np.nan  # group 2, vector 9: non-finite
+    H[3, 10, 2] = np.inf      # group 3: non-finite channel
+    d2 = dict(d, H=H, y=y)
+    ref = _group_oracle(d2, 0.5, 6)
+    desc = gpu_lib.make_desc(64, B, U, oracle.QPSK, y_per_H=YPH, t_max=6, alpha=0.5)
+    g = fused(gpu_lib, desc, H, y)
+    np.testing.assert_array_equal(g["status"], ref["status"])
+    ok = ref["status"] == 0
+    assert_L_parity(unpack_lower(g["L"][ok], N), ref["L"][ok])
+    bad = ~ok
+    assert np.all(g["sbar"][bad] == 1) and np.all(g["margin"][bad] == 0)
+    np.testing.assert_allclose(unpack_lower(g["L"][bad], N), ref["L"][bad], rtol=1e-6)
+
+
+@pytest.mark.parametrize("Bx,t_max,flags", [(30, 10, 0), (7, 3, 0), (128, 0, 0), (64, 8, 1)])
+def test_fused_ragged_and_flags(gpu_lib, Bx, t_max, flags):
+    d = sim.gen_mimo(Bx, U, oracle.QPSK, 8, 32, 8.0, 777 + Bx)
+    ref = _group_oracle(d, 0.7, t_max, pin_last=not flags)
+    desc = gpu_lib.make_desc(256, Bx, U, oracle.QPSK, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=32,
+                             t_max=t_max, flags=flags)
+    g = fused(gpu_lib, desc, d["H"], d["y"], tau=ref["tau"].astype(np.float32))
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+    np.testing.assert_array_equal(g["status"], ref["status"])
+
+
+def test_fused_rejects_unsupported(gpu_lib):
+    import torch
+    desc = gpu_lib.make_desc(64, 32, 8, oracle.QPSK, y_per_H=1, t_max=10)
+    with pytest.raises(gpu_lib.TaserError):
+        gpu_lib.run(desc, torch.zeros((64, 32, 8), dtype=torch.complex64, device="cuda"),
+                    torch.zeros((64, 32), dtype=torch.complex64, device="cuda"))
