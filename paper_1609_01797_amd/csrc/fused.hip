@@ -315,30 +315,54 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) nsq[mt][r] = 0.f;
 
-    // rows 0..31: V = L~ - 2 tau tril(L~ T~), restricted to the G~ block
-    sfor<0, 32>([&](auto ic) {
+    // Products of every row are independent (row i of V needs row i of L~
+    // only), so the MFMAs run ahead of the VALU epilogue: the last row's
+    // product is issued first and each row's epilogue trails the products
+    // of the next kAhead rows.
+    constexpr int kAhead = 2;
+    f4 lacc[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      lacc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lacc[mt] = mfma(A[mt][kt][s], l21[kt][s], lacc[mt]);
+    }
+    float cl = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cl += l21[mt][r] * ct[mt][r];
+
+    f4 ring[kAhead + 1][2];
+    auto product = [&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      f4 acc[2];
+      constexpr int SLOT = I % (kAhead + 1);
       sfor<0, 2>([&](auto mc) {
         constexpr int MT = decltype(mc)::value;
         if constexpr (16 * MT <= I) {
-          acc[MT] = f4{0.f, 0.f, 0.f, 0.f};
+          ring[SLOT][MT] = f4{0.f, 0.f, 0.f, 0.f};
           sfor<0, 2>([&](auto kc) {
             constexpr int KT = decltype(kc)::value;
             sfor<0, 4>([&](auto sc) {
               constexpr int S = decltype(sc)::value;
               if constexpr (16 * KT + 4 * S <= I)
-                acc[MT] = mfma(A[MT][KT][S], Lr[I][KT][S], acc[MT]);
+                ring[SLOT][MT] = mfma(A[MT][KT][S], Lr[I][KT][S], ring[SLOT][MT]);
             });
           });
         }
       });
+    };
+    auto epilogue = [&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int SLOT = I % (kAhead + 1);
       sfor<0, 2>([&](auto mc) {
         constexpr int MT = decltype(mc)::value;
         sfor<0, 4>([&](auto rc) {
           constexpr int R = decltype(rc)::value;
           if constexpr (16 * MT + 4 * R <= I) {
-            float x = fmaf(m2tau, acc[MT][R], Lr[I][MT][R]);
+            float x = fmaf(m2tau, ring[SLOT][MT][R], Lr[I][MT][R]);
             if constexpr (16 * MT + 4 * R + 3 > I) {
               if (g > I - 16 * MT - 4 * R) x = 0.f;   // strictly upper part
             }
@@ -347,34 +371,24 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
           }
         });
       });
+    };
+    sfor<0, kAhead>([&](auto ic) { product(ic); });
+    sfor<0, 32>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      if constexpr (I + kAhead < 32) product(std::integral_constant<int, I + kAhead>{});
+      epilogue(ic);
     });
 
-    // last row: l21^T G~ + l22 c~^T, and V_NN
-    float cl = 0.f;
+    // last row: V = l21 - 2 tau (l21^T G~ + l22 c~^T), and V_NN
+    cl = sum_groups(cl);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cl += l21[mt][r] * ct[mt][r];
-    cl = sum_groups(cl);
-    {
-      f4 acc[2];
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) acc[mt] = mfma(A[mt][kt][s], l21[kt][s], acc[mt]);
+      for (int r = 0; r < 4; ++r) {
+        const float x = fmaf(m2tau, fmaf(l22, ct[mt][r], lacc[mt][r]), l21[mt][r]);
+        l21[mt][r] = x;
+        nsq[mt][r] = fmaf(x, x, nsq[mt][r]);
       }
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float x = fmaf(m2tau, fmaf(l22, ct[mt][r], acc[mt][r]), l21[mt][r]);
-          l21[mt][r] = x;
-          nsq[mt][r] = fmaf(x, x, nsq[mt][r]);
-        }
-    }
     const float vnn = fmaf(m2tau, cl + l22, l22);   // T~_NN = 1
     if (!(vnn > 0.f)) st_bits |= TASER_VEC_VNN_NONPOS;
 
