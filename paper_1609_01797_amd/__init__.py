@@ -19,7 +19,8 @@ __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "
            "TAU_SPECTRAL", "TAU_GIVEN", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtaser.so")
+LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                      "libtaser.so")
 
 BPSK, QPSK = 1, 2
 COHERENT, JED = 0, 1

@@ -39,15 +39,35 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Sum over the four lanes that serve one vector (lanes n, n+16, n+32, n+48).
+// Sum over the four lanes that serve one vector (lanes n, n+16, n+32, n+48)
+// with the gfx950 lane-swap instructions (no LDS round trip).  With both
+// operands equal, the two results of a swap hold x and its partner's x in
+// every lane, so their sum is the pairwise sum: first across the two 32-lane
+// halves, then across adjacent 16-lane rows.
 __device__ __forceinline__ float sum_groups(float x) {
-  x += __shfl_xor(x, 16, 64);
-  x += __shfl_xor(x, 32, 64);
-  return x;
+  const unsigned u = __float_as_uint(x);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const unsigned w = __float_as_uint(y);
+  const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-constexpr int kLanczosSteps = 14;  // Krylov dimension for ||T~||_2
-constexpr int kLaguerreIters = 12;
+__device__ __forceinline__ int or_groups(int x) {
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  const unsigned y = h[0] | h[1];
+  const auto r = __builtin_amdgcn_permlane16_swap(y, y, false, false);
+  return (int)(r[0] | r[1]);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Krylov dimension for ||T~||_2.  Twelve steps of the plain float32
+// recurrence reach the float32 resolution of the top Ritz value on these
+// matrices; more steps start to produce ghost copies of it (loss of
+// orthogonality), which slows Laguerre's method down to linear convergence.
+constexpr int kLanczosSteps = 12;
+constexpr int kLaguerreIters = 8;
 
 // Largest eigenvalue of the symmetric tridiagonal (al, b2 = beta^2) of size M
 // by Laguerre's method from the Gershgorin upper bound.  The characteristic
@@ -67,7 +87,7 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
   for (int it = 0; it < kLaguerreIters; ++it) {
     float d = x - al[0];
     float e = 1.f, f = 0.f;
-    float id = 1.f / d;
+    float id = rcp(d);
     float G = e * id, Hs = G * G;
 #pragma unroll
     for (int k = 1; k < M; ++k) {
@@ -75,16 +95,18 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
       const float en = 1.f + b2[k - 1] * e * id * id;
       const float fn = b2[k - 1] * id * id * (f - 2.f * e * e * id);
       d = dn; e = en; f = fn;
-      id = 1.f / d;
+      id = rcp(d);
       const float r = e * id;
       G += r;
       Hs += r * r - f * id;
     }
     const float disc = fmaxf(0.f, (float)(M - 1) * ((float)M * Hs - G * G));
-    const float step = (float)M / (G + sqrtf(disc));
+    const float step = (float)M * rcp(G + sqrtf(disc));
     if (!(step > 0.f) || !isfinite(step)) break;
     x -= step;
-    if (step <= 1e-7f * x) break;
+    // cubic convergence: once a step is this small the next one would be
+    // below float32 resolution
+    if (step <= 1e-5f * x) break;
   }
   return x;
 }
@@ -106,19 +128,36 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
   // ---------------- preprocessing: G = H^H H, b = H^H y on MFMA ----------------
   f4 reG = {0.f, 0.f, 0.f, 0.f}, imG = reG, reb = reG, imb = reG;
   float ysq = 0.f;
-  for (int r0 = 0; r0 < B; r0 += 4) {
-    const int row = r0 + g;
-    const float2 h = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
-    const float2 y = row < B ? yv[row] : make_float2(0.f, 0.f);
-    reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
-    reG = mfma(h.y, h.y, reG);
-    imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
-    imG = mfma(h.y, -h.x, imG);
-    reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
-    reb = mfma(h.y, y.y, reb);
-    imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
-    imb = mfma(h.y, -y.x, imb);
-    ysq += y.x * y.x + y.y * y.y;
+  // Rows are consumed in batches of 8 row-quads; the next batch's loads are
+  // issued before the current batch's MFMAs so that load latency overlaps.
+  constexpr int kQ = 8;
+  float2 hc[kQ], yc[kQ], hnx[kQ], ynx[kQ];
+  auto load_batch = [&](int r0, float2 (&hb)[kQ], float2 (&yb)[kQ]) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int row = r0 + 4 * q + g;
+      hb[q] = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
+      yb[q] = row < B ? yv[row] : make_float2(0.f, 0.f);
+    }
+  };
+  load_batch(0, hc, yc);
+  for (int r0 = 0; r0 < B; r0 += 4 * kQ) {
+    if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, hnx, ynx);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const float2 h = hc[q], y = yc[q];
+      reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
+      reG = mfma(h.y, h.y, reG);
+      imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
+      imG = mfma(h.y, -h.x, imG);
+      reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
+      reb = mfma(h.y, y.y, reb);
+      imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
+      imb = mfma(h.y, -y.x, imb);
+      ysq += y.x * y.x + y.y * y.y;
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) { hc[q] = hnx[q]; yc[q] = ynx[q]; }
   }
   ysq = sum_groups(ysq);
 #pragma unroll
@@ -221,22 +260,25 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
     float scale = 0.f;
     sfor<0, kLanczosSteps>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      f4 acc[2];
+      // four independent accumulation chains (mt, kt) keep the MFMA pipe full
+      f4 acc[2][2];
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
+        for (int kt = 0; kt < 2; ++kt) acc[mt][kt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc[mt] = mfma(A[mt][kt][s], Q[kt][s], acc[mt]);
-      }
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int kt = 0; kt < 2; ++kt) acc[mt][kt] = mfma(A[mt][kt][s], Q[kt][s], acc[mt][kt]);
       float W[2][4];
       float cq = 0.f;
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          W[mt][r] = acc[mt][r] + ct[mt][r] * q32;
+          W[mt][r] = (acc[mt][0][r] + acc[mt][1][r]) + ct[mt][r] * q32;
           cq += ct[mt][r] * Q[mt][r];
         }
       float w32 = sum_groups(cq) + q32;
@@ -268,7 +310,7 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
         b2[j] = 0.f;
       }
       beta = sqrtf(bb);
-      const float ib = beta > 0.f ? 1.f / beta : 0.f;
+      const float ib = beta > 0.f ? rcp(beta) : 0.f;
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -438,9 +480,7 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
   }
 
   // ---------------- slicing and outputs ----------------
-  int bits = st_bits;
-  bits |= __shfl_xor(bits, 16, 64);
-  bits |= __shfl_xor(bits, 32, 64);
+  int bits = or_groups(st_bits);
   if (skip) bits = nonfinite ? TASER_VEC_NONFINITE : TASER_VEC_DEGENERATE;
 
   int8_t* sb = a.sbar + v * 32;
