@@ -55,6 +55,7 @@ typedef enum {
   TASER_ERR_ARG = -1,            /* null pointer, bad enum, bad alpha / t_max */
   TASER_ERR_SHAPE = -2,          /* sizes out of range or inconsistent */
   TASER_ERR_UNSUPPORTED = -3,    /* valid request this build does not implement */
+  TASER_ERR_WORKSPACE = -4,      /* workspace pointer NULL or smaller than required */
   TASER_ERR_DEVICE = -5          /* a HIP call or kernel launch failed */
 } taser_status_t;
 
@@ -139,16 +140,29 @@ taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const floa
 taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const float* D,
                             int8_t* sbar, float* margin, void* stream);
 
-/* The whole detector in one launch: build T, precondition, step size,
-   t_max iterations and slicing, with T~ and L~ kept on chip.  Same inputs as
-   taser_build_T; tau_in [V] is read when tau_mode == GIVEN (else may be NULL).
+/* Device workspace (bytes) that taser_run needs for this descriptor, written
+   to *bytes; 0 when the request needs none.  Host-only; returns the same
+   errors as taser_run would for the descriptor (TASER_ERR_UNSUPPORTED for a
+   shape the fused path does not cover). */
+taser_status_t taser_workspace_size(const taser_desc_t* desc, size_t* bytes);
+
+/* The whole detector (build T, precondition, step size, t_max iterations,
+   slicing) in one call: two kernels on `stream`, a preprocessing kernel that
+   leaves each channel group's preconditioned G~, border c~, D and tau in the
+   workspace, and the solve kernel that keeps L~ in registers.
+   Same inputs as taser_build_T; tau_in [V] is read when tau_mode == GIVEN
+   (else may be NULL).  ws: device buffer of at least
+   taser_workspace_size() bytes owned by the caller (contents on entry are
+   ignored; calls that share a workspace must not overlap).
    Outputs: sbar int8 [V][N-1]; margin float32 [V][N-1] or NULL; status [V];
    L_out [V][N(N+1)/2] float32 or NULL (written only when non-NULL).
-   Supported shapes: N-1 in {16, 32, 64} (other N return
-   TASER_ERR_UNSUPPORTED; use the staged calls). */
+   Supported: coherent QPSK with U = 16 (N = 33) and y_per_H a multiple of 16
+   (a wave detects the 16 vectors of one channel); other requests return
+   TASER_ERR_UNSUPPORTED (use the staged calls). */
 taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
                          const void* s0, const float* tau_in, int8_t* sbar, float* margin,
-                         int32_t* status, float* L_out, void* stream);
+                         int32_t* status, float* L_out, void* ws, size_t ws_bytes,
+                         void* stream);
 
 #ifdef __cplusplus
 }

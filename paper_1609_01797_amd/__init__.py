@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
 
 LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -29,7 +29,7 @@ TAU_SPECTRAL, TAU_GIVEN = 0, 1
 FLAG_LITERAL_LAST = 1
 VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS = 1, 2, 4, 8
 
-OK, ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_DEVICE = 0, -1, -2, -3, -5
+OK, ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, -1, -2, -3, -4, -5
 
 
 class TaserError(RuntimeError):
@@ -72,8 +72,10 @@ def load():
     lib.taser_solve.argtypes = [D, _P, _P, _P, _P, _P, _P]
     lib.taser_detect.restype = ctypes.c_int
     lib.taser_detect.argtypes = [D, _P, _P, _P, _P, _P]
+    lib.taser_workspace_size.restype = ctypes.c_int
+    lib.taser_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
     lib.taser_run.restype = ctypes.c_int
-    lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     _lib = lib
     return lib
 
@@ -194,9 +196,31 @@ def detect(desc: Desc, L, D, want_margin=True):
     return sbar, margin
 
 
-def run(desc: Desc, H, y, s0=None, tau=None, want_margin=False, want_L=False, out=None):
-    """The fused single-launch detector.  Returns dict sbar, status (+ margin,
-    L when requested).  ``out`` may hold preallocated tensors to reuse."""
+def workspace_size(desc: Desc) -> int:
+    """Bytes of device workspace ``run`` needs for ``desc``."""
+    n = ctypes.c_size_t(0)
+    _raise(load().taser_workspace_size(ctypes.byref(desc), ctypes.byref(n)))
+    return int(n.value)
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes, device):
+    """A cached device buffer of at least ``nbytes`` per device (torch-allocated)."""
+    torch = _torch()
+    key = (device.type, device.index if device.index is not None else torch.cuda.current_device())
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def run(desc: Desc, H, y, s0=None, tau=None, want_margin=False, want_L=False, out=None, ws=None):
+    """The fused detector.  Returns dict sbar, status (+ margin, L when
+    requested).  ``out`` may hold preallocated tensors to reuse; ``ws`` a
+    uint8 device workspace (a cached one is used otherwise)."""
     torch = _torch()
     lib = load()
     V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
@@ -211,11 +235,17 @@ def run(desc: Desc, H, y, s0=None, tau=None, want_margin=False, want_L=False, ou
         res["margin"] = torch.empty((V, N - 1), dtype=torch.float32, device=dev)
     if want_L and "L" not in res:
         res["L"] = torch.empty((V, N * (N + 1) // 2), dtype=torch.float32, device=dev)
+    nbytes = workspace_size(desc)
+    if ws is None:
+        ws = _workspace(nbytes, dev)
+    if ws.dtype != torch.uint8 or not ws.is_cuda or ws.numel() < nbytes:
+        raise ValueError(f"workspace must be a uint8 CUDA tensor of at least {nbytes} bytes")
     st = lib.taser_run(ctypes.byref(desc), ph, py, ps, pt,
                        _need(res["sbar"], torch.int8, V * (N - 1), "sbar"),
                        _opt(res.get("margin") if want_margin else None, torch.float32, V * (N - 1), "margin"),
                        _need(res["status"], torch.int32, V, "status"),
                        _opt(res.get("L") if want_L else None, torch.float32, V * N * (N + 1) // 2, "L"),
+                       ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                        _stream(dev))
     _raise(st)
     return res

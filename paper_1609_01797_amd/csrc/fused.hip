@@ -62,6 +62,43 @@ __device__ __forceinline__ int or_groups(int x) {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// 16-bit operands for the BF16 / FP16 products: four values packed in two
+// dwords, element e holding MFMA K position 4 (lane / 16) + e.
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+// Two float32 values to packed 16-bit (round to nearest even): one
+// v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32, visible to the compiler's hazard
+// tracking (the conversion feeds an MFMA source directly).
+template <int P>
+__device__ __forceinline__ unsigned cvt_pk(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 x = {lo, hi};
+  if constexpr (P == TASER_PREC_BF16) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(x, b2));
+  } else {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(x, h2));
+  }
+}
+
+template <int P>
+__device__ __forceinline__ u2 pack4(float x0, float x1, float x2, float x3) {
+  return u2{cvt_pk<P>(x0, x1), cvt_pk<P>(x2, x3)};
+}
+
+template <int P>
+__device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
+  if constexpr (P == TASER_PREC_BF16)
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a),
+                                                     __builtin_bit_cast(s4, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a),
+                                                 __builtin_bit_cast(h4, b), c, 0, 0, 0);
+}
+
 // Krylov dimension for ||T~||_2.  Twelve steps of the plain float32
 // recurrence reach the float32 resolution of the top Ritz value on these
 // matrices; more steps start to produce ghost copies of it (loss of
@@ -111,7 +148,15 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
   return x;
 }
 
-__global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
+// Workspace per channel group (floats): the MFMA A operands of G~, the border
+// c~, the column scales D and per-lane D_NN, tau and flags, stored
+// register-major ([register][lane]) so both kernels move them coalesced.
+constexpr int kWsA = 0, kWsC = 1024, kWsD = 1536, kWsDN = 1792, kWsTau = 1856, kWsFlag = 1920;
+constexpr int kWsFloats = 2048;
+
+// Preprocessing of one channel group (one wave): T~ in bordered form and the
+// step size, stored to the workspace in the register layout of the solve.
+__global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
   __shared__ float2 Gs[16 * 16];   // G = H^H H, [row][col]
   __shared__ float2 bs[16 * 16];   // b = H^H y, [user][vector]
   __shared__ float yy2[16];        // ||y||^2 per vector
@@ -321,7 +366,66 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
     const float lam = tridiag_top<kLanczosSteps>(al, b2);
     tau = a.alpha / (lam > 0.f ? lam : 1.f);
   }
+  // ---------------- hand the group's state to the solve kernel ----------------
+  float* ws = a.ws + (long long)blockIdx.x * kWsFloats;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ws[kWsA + ((mt * 2 + kt) * 4 + s) * 64 + lane] = A[mt][kt][s];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ws[kWsC + (mt * 4 + r) * 64 + lane] = ct[mt][r];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ws[kWsD + r * 64 + lane] = Dc[r];
+  ws[kWsDN + lane] = DN;
+  ws[kWsTau + lane] = tau;
+  ws[kWsFlag + lane] = __int_as_float((nonfinite ? 2 : 0) | (degenerate ? 1 : 0));
+}
+
+// Algorithm 1 for one channel group (one wave), from the state the prep
+// kernel left in the workspace.  P selects the arithmetic of the L~ T~
+// products: float32 MFMAs (16x16x4, K-steps of four columns skipped where L~
+// is zero), or BF16 / FP16 operands with float32 accumulation (16x16x16, one
+// MFMA per 16-column tile).  V, the norms, rsqrt and the master copy of L~
+// are float32 in every case.
+template <int P>
+__global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
+  const int lane = threadIdx.x;
+  const int n = lane & 15;
+  const int g = lane >> 4;
+  const long long v = (long long)blockIdx.x * 16 + n;
+  const float* ws = a.ws + (long long)blockIdx.x * kWsFloats;
+  float A[2][2][4], ct[2][4], Dc[4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) A[mt][kt][s] = ws[kWsA + ((mt * 2 + kt) * 4 + s) * 64 + lane];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ct[mt][r] = ws[kWsC + (mt * 4 + r) * 64 + lane];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Dc[r] = ws[kWsD + r * 64 + lane];
+  const float DN = ws[kWsDN + lane];
+  const float tau = ws[kWsTau + lane];
+  const int fl = __float_as_int(ws[kWsFlag + lane]);
+  const bool nonfinite = (fl & 2) != 0;
+  const bool skip = fl != 0;
   const float m2tau = -2.f * tau;
+  constexpr bool k16 = P != TASER_PREC_F32;
+  u2 Ah[2][2];
+  if constexpr (k16) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+        Ah[mt][kt] = pack4<P>(A[mt][kt][0], A[mt][kt][1], A[mt][kt][2], A[mt][kt][3]);
+  }
 
   // ---------------- Algorithm 1: L~(0) = D, t_max FBS steps ----------------
   // Lr[i][mt][r] is stored only where 16 mt + 4 r <= i (otherwise the whole
@@ -363,13 +467,23 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
     // of the next kAhead rows.
     constexpr int kAhead = 2;
     f4 lacc[2];
+    if constexpr (k16) {
+      const u2 b0 = pack4<P>(l21[0][0], l21[0][1], l21[0][2], l21[0][3]);
+      const u2 b1 = pack4<P>(l21[1][0], l21[1][1], l21[1][2], l21[1][3]);
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      lacc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int mt = 0; mt < 2; ++mt) {
+        lacc[mt] = mfma16<P>(Ah[mt][0], b0, f4{0.f, 0.f, 0.f, 0.f});
+        lacc[mt] = mfma16<P>(Ah[mt][1], b1, lacc[mt]);
+      }
+    } else {
 #pragma unroll
-      for (int kt = 0; kt < 2; ++kt)
+      for (int mt = 0; mt < 2; ++mt) {
+        lacc[mt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) lacc[mt] = mfma(A[mt][kt][s], l21[kt][s], lacc[mt]);
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) lacc[mt] = mfma(A[mt][kt][s], l21[kt][s], lacc[mt]);
+      }
     }
     float cl = 0.f;
 #pragma unroll
@@ -381,6 +495,26 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
     auto product = [&](auto ic) {
       constexpr int I = decltype(ic)::value;
       constexpr int SLOT = I % (kAhead + 1);
+      if constexpr (k16) {
+        auto Lv = [&](auto kc, auto rc) {
+          constexpr int KT = decltype(kc)::value, R = decltype(rc)::value;
+          if constexpr (16 * KT + 4 * R <= I) return Lr[I][KT][R];
+          else return 0.f;
+        };
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        using C3 = std::integral_constant<int, 3>;
+        const u2 b0 = pack4<P>(Lv(C0{}, C0{}), Lv(C0{}, C1{}), Lv(C0{}, C2{}), Lv(C0{}, C3{}));
+        ring[SLOT][0] = mfma16<P>(Ah[0][0], b0, f4{0.f, 0.f, 0.f, 0.f});
+        if constexpr (I >= 16) {
+          const u2 b1 = pack4<P>(Lv(C1{}, C0{}), Lv(C1{}, C1{}), Lv(C1{}, C2{}), Lv(C1{}, C3{}));
+          ring[SLOT][0] = mfma16<P>(Ah[0][1], b1, ring[SLOT][0]);
+          ring[SLOT][1] = mfma16<P>(Ah[1][0], b0, f4{0.f, 0.f, 0.f, 0.f});
+          ring[SLOT][1] = mfma16<P>(Ah[1][1], b1, ring[SLOT][1]);
+        }
+        return;
+      }
       sfor<0, 2>([&](auto mc) {
         constexpr int MT = decltype(mc)::value;
         if constexpr (16 * MT <= I) {
@@ -524,13 +658,25 @@ __global__ __launch_bounds__(64) void fused_group_qpsk16(FusedArgs a) {
 }  // namespace
 
 bool fused_supported(const FusedArgs& a) {
-  return a.mode == TASER_COHERENT && a.mod == TASER_QPSK && a.U == 16 && a.prec == TASER_PREC_F32 &&
-         a.y_per_H % 16 == 0 && a.B >= 1;
+  return a.mode == TASER_COHERENT && a.mod == TASER_QPSK && a.U == 16 && a.y_per_H % 16 == 0 &&
+         a.B >= 1;
+}
+
+size_t fused_workspace_bytes(const FusedArgs& a) {
+  return (size_t)(a.V / 16) * kWsFloats * sizeof(float);
 }
 
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
   const int groups = a.V / 16;
-  hipLaunchKernelGGL(fused_group_qpsk16, dim3(groups), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(prep_group_qpsk16, dim3(groups), dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.prec == TASER_PREC_BF16)
+    hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_BF16>, dim3(groups), dim3(64), 0, s, a);
+  else if (a.prec == TASER_PREC_F16)
+    hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_F16>, dim3(groups), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_F32>, dim3(groups), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ const char* taser_status_string(int status) {
     case TASER_ERR_ARG: return "TASER_ERR_ARG: invalid argument (null pointer, enum, alpha or t_max)";
     case TASER_ERR_SHAPE: return "TASER_ERR_SHAPE: sizes out of range or inconsistent";
     case TASER_ERR_UNSUPPORTED: return "TASER_ERR_UNSUPPORTED: request not implemented for this shape or precision";
+    case TASER_ERR_WORKSPACE: return "TASER_ERR_WORKSPACE: workspace missing or too small";
     case TASER_ERR_DEVICE: return "TASER_ERR_DEVICE: a HIP call or kernel launch failed";
     default: return "TASER: unknown status";
   }
@@ -113,27 +114,46 @@ taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const floa
              : TASER_ERR_DEVICE;
 }
 
-taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y, const void* s0,
-                         const float* tau_in, int8_t* sbar, float* margin, int32_t* status,
-                         float* L_out, void* stream) {
+static taser_status_t fused_args(const taser_desc_t* desc, FusedArgs* a) {
   taser_status_t st = check(desc);
   if (st != TASER_OK) return st;
-  FusedArgs a{};
-  a.V = desc->num_vectors; a.B = desc->B; a.U = desc->U;
-  a.N = taser_problem_size(desc->U, desc->mod);
-  a.mod = desc->mod; a.mode = desc->mode; a.y_per_H = desc->y_per_H; a.t_max = desc->t_max;
-  a.flags = desc->flags; a.tau_mode = desc->tau_mode; a.prec = desc->prec; a.alpha = desc->alpha;
-  if (!fused_supported(a)) return TASER_ERR_UNSUPPORTED;
+  *a = FusedArgs{};
+  a->V = desc->num_vectors; a->B = desc->B; a->U = desc->U;
+  a->N = taser_problem_size(desc->U, desc->mod);
+  a->mod = desc->mod; a->mode = desc->mode; a->y_per_H = desc->y_per_H; a->t_max = desc->t_max;
+  a->flags = desc->flags; a->tau_mode = desc->tau_mode; a->prec = desc->prec; a->alpha = desc->alpha;
+  if (!fused_supported(*a)) return TASER_ERR_UNSUPPORTED;
+  return TASER_OK;
+}
+
+taser_status_t taser_workspace_size(const taser_desc_t* desc, size_t* bytes) {
+  if (!bytes) return TASER_ERR_ARG;
+  FusedArgs a;
+  taser_status_t st = fused_args(desc, &a);
+  if (st != TASER_OK) return st;
+  *bytes = fused_workspace_bytes(a);
+  return TASER_OK;
+}
+
+taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y, const void* s0,
+                         const float* tau_in, int8_t* sbar, float* margin, int32_t* status,
+                         float* L_out, void* ws, size_t ws_bytes, void* stream) {
+  FusedArgs a;
+  taser_status_t st = fused_args(desc, &a);
+  if (st != TASER_OK) return st;
   if (a.V == 0) return TASER_OK;
   const bool jed = desc->mode == TASER_JED;
   if (!y || !sbar || !status) return TASER_ERR_ARG;
   if (!jed && !H) return TASER_ERR_ARG;
   if (jed && !s0) return TASER_ERR_ARG;
   if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
+  const size_t need = fused_workspace_bytes(a);
+  if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
   a.H = static_cast<const float2*>(H);
   a.y = static_cast<const float2*>(y);
   a.s0 = static_cast<const float2*>(s0);
   a.tau_in = tau_in; a.sbar = sbar; a.margin = margin; a.status = status; a.L_out = L_out;
+  a.ws = static_cast<float*>(ws);
   return launch_fused(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
                                                                         : TASER_ERR_DEVICE;
 }

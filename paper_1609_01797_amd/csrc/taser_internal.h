@@ -43,8 +43,10 @@ struct FusedArgs {
   float* margin;
   int32_t* status;
   float* L_out;
+  float* ws;           // workspace, fused_workspace_bytes(a) bytes
 };
 bool fused_supported(const FusedArgs& a);
+size_t fused_workspace_bytes(const FusedArgs& a);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
 
 // LDS bytes the staged build kernel needs (0 if the shape does not fit).

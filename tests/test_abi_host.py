@@ -74,7 +74,7 @@ def test_entry_points_reject_before_any_launch():
     assert lib.taser_build_T(ctypes.byref(bad), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
     assert lib.taser_solve(ctypes.byref(bad), z, z, z, z, z, z) == taser.ERR_ARG
     assert lib.taser_detect(ctypes.byref(bad), z, z, z, z, z) == taser.ERR_ARG
-    assert lib.taser_run(ctypes.byref(bad), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
+    assert lib.taser_run(ctypes.byref(bad), z, z, z, z, z, z, z, z, z, 0, z) == taser.ERR_ARG
     good = _d()
     # valid descriptor, null buffers: rejected synchronously
     assert lib.taser_build_T(ctypes.byref(good), z, z, z, z, z, z, z, z, z) == taser.ERR_ARG
@@ -89,6 +89,21 @@ def test_entry_points_reject_before_any_launch():
     assert lib.taser_solve(ctypes.byref(_d(prec=taser.PREC_BF16)), z, z, z, z, z, z) == taser.ERR_UNSUPPORTED
     # a channel too large for the staged build's LDS copy
     assert lib.taser_build_T(ctypes.byref(_d(B=4096, U=16)), z, z, z, z, z, z, z, z, z) in (taser.ERR_ARG, taser.ERR_UNSUPPORTED)
+
+
+def test_workspace_size_query():
+    lib = taser.load()
+    n = ctypes.c_size_t(0)
+    d = taser.make_desc(65536, 128, 16, taser.QPSK, y_per_H=16)
+    assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
+    assert n.value == 4096 * 2048 * 4
+    assert lib.taser_workspace_size(ctypes.byref(d), None) == taser.ERR_ARG
+    other = taser.make_desc(64, 32, 8, taser.QPSK)
+    assert lib.taser_workspace_size(ctypes.byref(other), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
+    # a run with a missing workspace is rejected before any launch
+    z = ctypes.c_void_p(0)
+    one = ctypes.c_void_p(16)   # non-null but never dereferenced: the call fails first
+    assert lib.taser_run(ctypes.byref(d), one, one, z, z, one, z, one, z, z, 0, z) == taser.ERR_WORKSPACE
 
 
 def test_binding_refuses_cpu_tensors():
