@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
-"""Throughput of batched TASER detection on one MI355X.
+"""Throughput and accuracy of batched TASER detection on one MI355X.
 
 Workload: coherent MU-MIMO uplink, B = 128 receive antennas, U = 16 QPSK
 users (real problem size N = 33), 4,096 independent Rayleigh channels each
-shared by 16 received vectors (65,536 vectors), SNR 10 dB, t_max = 10,
-tau = alpha/||T~||_2 computed on the GPU.  One step is one launch of the
-fused detector over the whole batch: build T, precondition, step size,
-t_max forward-backward iterations and slicing (inputs resident in HBM).
+shared by 16 received vectors (65,536 vectors), t_max = 10, alpha = 0.5,
+tau = alpha/||T~||_2 computed on the GPU.  One step is the whole detector
+over the batch with inputs resident in HBM: the preparation kernel (T,
+Jacobi preconditioning, step size) and the solve kernel (t_max iterations,
+slicing).  The headline value is the BF16-product path; the FP32 and FP16
+paths are timed the same way.
 
-Prints one JSON line.  ``roofline`` compares the algorithmic flops of one
-launch (loop flops per vector in Table I's counting plus the T-assembly
-flops; the spectral-norm estimate is excluded) with the float32 MFMA peak.
-``cpu_baseline`` times the FP64 numpy oracle on the same batch with one
-single-threaded worker process per host core (capped at 16).
+Accuracy: the three GPU paths and the FP64 oracle run on the same inputs at
+several SNRs (paired); the BER gap in dB is read at the SNR where the
+oracle's BER crosses 1e-3 (log-linear interpolation).
+
+Prints one JSON line.  ``roofline`` is for the kernel that takes the larger
+share of the headline step; the work counted is algorithmic (see
+loop_flops / build_flops / input_bytes); the spectral-norm estimate is
+excluded.  ``cpu_baseline`` times the FP64 numpy oracle on the SNR sample
+with one single-threaded worker process per host core (capped at 16).
 """
 from __future__ import annotations
 
@@ -35,24 +41,44 @@ B, U, MOD, N = 128, 16, 2, 33
 NUM_H, Y_PER_H = 4096, 16
 V = NUM_H * Y_PER_H
 T_MAX = 10
-SNR_DB = 10.0
 ALPHA = 0.5
-PEAK_FP32_TFLOPS = 157.3   # MI355X dense float32 matrix (and vector) peak
+SNR_TIMED = 10.0
+SNR_SWEEP = [-4.0, -2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0, 14.0, 16.0, 18.0, 20.0]
+SNR_ORACLE = [-4.0, -2.0, 0.0, 2.0, 4.0, 10.0]      # errors vanish above 4 dB at this size
+BER_REF = 1e-3
+PEAK = {"mfma_fp32": 157.3, "alu_fp32": 157.3, "hbm": 8000.0}   # TFLOP/s, GB/s (MI355X datasheet)
+PRECS = (("bf16", 1), ("fp32", 0), ("fp16", 2))
 
 
 def loop_flops(N, t_max):
     """Algorithmic flops of t_max iterations for one vector: the tril product
     (sum_i i^2 multiply-adds), squared column norms (N(N+1)/2 multiply-adds),
-    the column scaling (N(N+1)/2) and N rsqrt-times-D pairs."""
+    the column scaling (N(N+1)/2) and N rsqrt-times-D pairs.  The
+    multiplications are exactly Table I's count."""
     s2 = N * (N + 1) * (2 * N + 1) // 6
     return t_max * (2 * s2 + 3 * N * (N + 1) // 2 + 2 * N)
+
+
+def loop_product_flops(N, t_max):
+    s2 = N * (N + 1) * (2 * N + 1) // 6
+    return t_max * 2 * s2
 
 
 def build_flops(B, U, N, y_per_H):
     """Algorithmic flops of assembling T~ for one vector: H^H y (8BU),
     ||y||^2 (4B), the Hermitian Gram H^H H shared by y_per_H vectors
-    (8B U(U+1)/2 / y_per_H), and scaling the last column and the shared block."""
+    (8B U(U+1)/2 / y_per_H), and scaling the border and the shared block."""
     return 8 * B * U + 4 * B + (8 * B * U * (U + 1) // 2) / y_per_H + 2 * (N - 1) + 2 * (N - 1) ** 2 / y_per_H
+
+
+def input_bytes(B, U, y_per_H):
+    """HBM bytes one vector's detection must read and write: its share of H,
+    y, the int8 decisions and the int32 status."""
+    return 8 * B * U / y_per_H + 8 * B + (N - 1) + 4
+
+
+def sbar_of(s):
+    return np.concatenate([s.real, s.imag], axis=1).astype(np.int8)
 
 
 def _oracle_chunk(args):
@@ -72,42 +98,58 @@ def _oracle_chunk(args):
     return lo, np.concatenate(out, axis=0)
 
 
-def cpu_baseline(d, workdir):
-    """FP64 oracle over the whole batch with single-threaded worker processes.
-    Runs before the GPU is touched (workers are forked)."""
+def cpu_baseline(data, workdir):
+    """The FP64 oracle, unchanged, over every vector of the SNR sample, with
+    single-threaded worker processes.  Runs before the GPU is touched."""
     import multiprocessing as mp
     cores = max(1, min(os.cpu_count() or 1, 16))
     os.makedirs(workdir, exist_ok=True)
-    Hpath, ypath = os.path.join(workdir, "H.npy"), os.path.join(workdir, "y.npy")
-    np.save(Hpath, d["H"])
-    np.save(ypath, d["y"])
     step = (V + cores - 1) // cores
     step = ((step + Y_PER_H - 1) // Y_PER_H) * Y_PER_H
-    jobs = [(lo, min(V, lo + step), Hpath, ypath) for lo in range(0, V, step)]
-    t0 = time.perf_counter()
+    decisions = {}
+    total = 0.0
     with mp.get_context("fork").Pool(cores) as pool:
-        parts = pool.map(_oracle_chunk, jobs)
-    dt = time.perf_counter() - t0
-    parts.sort(key=lambda p: p[0])
-    sbar = np.concatenate([p[1] for p in parts], axis=0)
-    os.remove(Hpath)
-    os.remove(ypath)
-    return {"value": V / dt, "unit": "vectors/s", "cores": cores, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"all {V} vectors of the workload, FP64 numpy oracle (tau spectral via "
-                      f"LAPACK eigvalsh), {cores} single-threaded worker processes"}, sbar
+        for snr in SNR_ORACLE:
+            d = data[snr]
+            Hpath, ypath = os.path.join(workdir, "H.npy"), os.path.join(workdir, "y.npy")
+            np.save(Hpath, d["H"])
+            np.save(ypath, d["y"])
+            jobs = [(lo, min(V, lo + step), Hpath, ypath) for lo in range(0, V, step)]
+            t0 = time.perf_counter()
+            parts = pool.map(_oracle_chunk, jobs)
+            total += time.perf_counter() - t0
+            parts.sort(key=lambda p: p[0])
+            decisions[snr] = np.concatenate([p[1] for p in parts], axis=0)
+            os.remove(Hpath)
+            os.remove(ypath)
+    n = V * len(SNR_ORACLE)
+    return {"value": n / total, "unit": "vectors/s", "cores": cores, "kind": "oracle",
+            "seconds": total,
+            "sample": f"{len(SNR_ORACLE)} SNR points x {V} vectors of the workload "
+                      f"(SNR dB {SNR_ORACLE}), FP64 numpy oracle with LAPACK eigvalsh for tau, "
+                      f"{cores} single-threaded worker processes"}, decisions
 
 
-def traffic_from_profile(src_hash):
+def snr_at(snrs, bers, target):
+    """SNR where log10(BER) crosses log10(target), linear interpolation
+    between the bracketing points; None if it is not bracketed."""
+    for (s0, b0), (s1, b1) in zip(zip(snrs, bers), zip(snrs[1:], bers[1:])):
+        if b0 >= target > b1 and b1 > 0:
+            l0, l1, lt = np.log10(b0), np.log10(b1), np.log10(target)
+            return s0 + (s1 - s0) * (l0 - lt) / (l0 - l1)
+    return None
+
+
+def traffic_from_profile(src_hash, kernel):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "fused_group_qpsk16_128x16_traffic.json")
+    p = os.path.join(ROOT, "profiles", "fused_128x16_traffic.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
     if rec.get("source_sha256") != src_hash:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(kernel)
 
 
 def main():
@@ -116,10 +158,16 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ber", action="store_true", help="skip the SNR sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this detector runs on one GPU; --gpus {args.gpus} is not supported "
+              "(every vector is independent, so more GPUs would shard the batch by channel group)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         import torch
         nbytes = 512 << 20
@@ -130,89 +178,137 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
         return
-    if args.gpus != 1:
-        print(f"bench.py: this detector runs on one GPU; --gpus {args.gpus} is not supported "
-              "(every vector is independent, so more GPUs would shard the batch by channel group)",
-              file=sys.stderr)
-        sys.exit(2)
 
-    d = sim.gen_mimo(B, U, MOD, NUM_H, Y_PER_H, SNR_DB, sim.seed_for(2, snr_index=5))
-    s_true = d["s"]
-    sbar_true = np.concatenate([s_true.real, s_true.imag], axis=1).astype(np.int8)
+    snrs = [SNR_TIMED] if args.no_ber else SNR_SWEEP
+    data = {snr: sim.gen_mimo(B, U, MOD, NUM_H, Y_PER_H, snr, sim.seed_for(2, snr_index=int(snr) + 10))
+            for snr in snrs}
 
-    cpu, sbar_cpu = (None, None)
-    if not args.no_cpu_baseline:
-        cpu, sbar_cpu = cpu_baseline(d, os.path.join(ROOT, "gpurun_out", "bench_tmp"))
+    cpu, oracle_sbar = None, {}
+    if not args.no_cpu_baseline and not args.no_ber:
+        cpu, oracle_sbar = cpu_baseline(data, os.path.join(ROOT, "gpurun_out", "bench_tmp"))
 
     import torch
     import paper_1609_01797_amd as taser
     taser.load()
     dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    # ---------------- accuracy sweep (paired inputs) ----------------
+    ber = {name: [] for name, _ in PRECS}
+    flips = {name: {} for name, _ in PRECS}
+    for snr in snrs:
+        d = data[snr]
+        H = torch.from_numpy(d["H"]).to(dev)
+        y = torch.from_numpy(d["y"]).to(dev)
+        truth = sbar_of(d["s"])
+        for name, prec in PRECS:
+            desc = taser.make_desc(V, B, U, MOD, prec=prec, y_per_H=Y_PER_H, t_max=T_MAX, alpha=ALPHA)
+            sb = taser.run(desc, H, y)["sbar"].cpu().numpy()
+            ber[name].append(float(np.mean(sb != truth)))
+            if snr in oracle_sbar:
+                flips[name][str(snr)] = int(np.count_nonzero(sb != oracle_sbar[snr]))
+    ber_fp64 = ([float(np.mean(oracle_sbar[s] != sbar_of(data[s]["s"]))) for s in SNR_ORACLE]
+                if oracle_sbar else [])
+
+    # ---------------- throughput at the timed SNR ----------------
+    d = data[SNR_TIMED]
     H = torch.from_numpy(d["H"]).to(dev)
     y = torch.from_numpy(d["y"]).to(dev)
-    desc = taser.make_desc(V, B, U, MOD, prec=taser.PREC_F32, tau_mode=taser.TAU_SPECTRAL,
-                           y_per_H=Y_PER_H, t_max=T_MAX, alpha=ALPHA)
-    out = {}
-    for _ in range(args.warmup):
-        taser.run(desc, H, y, out=out)
-    torch.cuda.synchronize()
+    timing = {}
+    for name, prec in PRECS:
+        desc = taser.make_desc(V, B, U, MOD, prec=prec, y_per_H=Y_PER_H, t_max=T_MAX, alpha=ALPHA)
+        ws = torch.empty(taser.workspace_size(desc), dtype=torch.uint8, device=dev)
+        out = {}
+        for _ in range(args.warmup):
+            taser.run_prep(desc, H, y, out=out, ws=ws)
+            taser.run_solve(desc, out, ws=ws)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            taser.run_prep(desc, H, y, out=out, ws=ws)
+            ev[k][1].record(stream)
+            taser.run_solve(desc, out, ws=ws)
+            ev[k][2].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = t0.elapsed_time(t1) / args.steps
+        prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        solve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        timing[name] = {"ms_per_step": ms_step, "vectors_per_s": V / (ms_step * 1e-3),
+                        "prep_kernel_ms": prep_ms, "solve_kernel_ms": solve_ms,
+                        "status_nonzero": int(torch.count_nonzero(out["status"]).item())}
 
-    stream = torch.cuda.current_stream(dev)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        taser.run(desc, H, y, out=out)
-        ev[k][1].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    ms_total = t_start.elapsed_time(t_end)
-    ms_per_step = ms_total / args.steps
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # ---------------- roofline of the dominant kernel of the headline path ----------------
+    src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_1609_01797_amd", "csrc", "fused.hip"),
+                                   "rb").read()).hexdigest()
+    head = timing["bf16"]
+    if head["solve_kernel_ms"] >= head["prep_kernel_ms"]:
+        # BF16 products on MFMA need far less time at 2.5 PFLOP/s than the
+        # float32 prox needs on the vector ALUs: the prox bounds the kernel.
+        work = (loop_flops(N, T_MAX) - loop_product_flops(N, T_MAX)) * V
+        roof = {"bound": "alu", "kernel": "solve_group_qpsk16<bf16>", "kernel_ms": head["solve_kernel_ms"],
+                "achieved": work / (head["solve_kernel_ms"] * 1e-3) / 1e12, "peak": PEAK["alu_fp32"],
+                "unit": "TFLOP/s", "work_per_vector": work / V,
+                "work": "prox flops (squared norms, scaling, rsqrt*D); the products run on bf16 MFMA"}
+    else:
+        # preparation: 12.6 flop/B, below the 19.7 flop/B float32 ridge -> HBM bound
+        nbytes = input_bytes(B, U, Y_PER_H) * V
+        roof = {"bound": "hbm", "kernel": "prep_group_qpsk16", "kernel_ms": head["prep_kernel_ms"],
+                "achieved": nbytes / (head["prep_kernel_ms"] * 1e-3) / 1e9, "peak": PEAK["hbm"],
+                "unit": "GB/s", "work_per_vector": nbytes / V,
+                "work": "bytes of H (shared by 16 vectors), y, decisions and status"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic_from_profile(src_hash, roof["kernel"])
+    fp32 = timing["fp32"]
+    fp32_roof = {"bound": "mfma", "kernel": "solve_group_qpsk16<fp32>", "kernel_ms": fp32["solve_kernel_ms"],
+                 "achieved": loop_flops(N, T_MAX) * V / (fp32["solve_kernel_ms"] * 1e-3) / 1e12,
+                 "peak": PEAK["mfma_fp32"], "unit": "TFLOP/s"}
+    fp32_roof["frac"] = fp32_roof["achieved"] / fp32_roof["peak"]
+    whole = (loop_flops(N, T_MAX) + build_flops(B, U, N, Y_PER_H)) * V
+    fp32["whole_step_tflops"] = whole / (fp32["ms_per_step"] * 1e-3) / 1e12
+    fp32["whole_step_frac_fp32_peak"] = fp32["whole_step_tflops"] / PEAK["mfma_fp32"]
+    fp32["roofline_solve"] = fp32_roof
 
-    sbar_gpu = out["sbar"].cpu().numpy()
-    status = out["status"].cpu().numpy()
+    accuracy = {"snr_db": snrs, "ber": ber, "bits_per_point": V * (N - 1),
+                "paired_bit_flips_vs_fp64": flips}
+    if ber_fp64:
+        accuracy["snr_db_fp64"] = SNR_ORACLE
+        accuracy["ber"]["fp64"] = ber_fp64
+        s64 = snr_at(SNR_ORACLE, ber_fp64, BER_REF)
+        gaps = {}
+        for name, _ in PRECS:
+            idx = [snrs.index(s) for s in SNR_ORACLE]
+            sp = snr_at(SNR_ORACLE, [ber[name][i] for i in idx], BER_REF)
+            gaps[name] = None if (s64 is None or sp is None) else sp - s64
+        accuracy["ber_gap_db_at_1e-3"] = gaps
+        accuracy["fp64_snr_db_at_1e-3"] = s64
 
-    flops_vec = loop_flops(N, T_MAX) + build_flops(B, U, N, Y_PER_H)
-    flops_launch = flops_vec * V
-    achieved = flops_launch / (kern_ms * 1e-3) / 1e12
-    src = open(os.path.join(ROOT, "paper_1609_01797_amd", "csrc", "fused.hip"), "rb").read()
-    src_hash = hashlib.sha256(src).hexdigest()
-    quality = {"snr_db": SNR_DB,
-               "ber_fp32_gpu": float(np.mean(sbar_gpu != sbar_true)),
-               "bits": int(sbar_true.size),
-               "status_nonzero": int(np.count_nonzero(status))}
-    if sbar_cpu is not None:
-        quality["ber_fp64_oracle"] = float(np.mean(sbar_cpu != sbar_true))
-        quality["fp32_vs_fp64_bit_disagreements"] = int(np.count_nonzero(sbar_cpu != sbar_gpu))
     rec = {
         "metric": METRIC,
-        "value": V / (ms_per_step * 1e-3),
+        "value": head["vectors_per_s"],
         "unit": "vectors/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "taser_coherent_128x16_qpsk_tmax10_65536vec_16perH",
                    "B": B, "U": U, "modulation": "QPSK", "N": N, "vectors": V, "y_per_H": Y_PER_H,
-                   "t_max": T_MAX, "snr_db": SNR_DB, "alpha": ALPHA, "tau": "spectral",
-                   "precision": "fp32 MFMA products, fp32 prox"},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": traffic_from_profile(src_hash),
-                     "kernel": "fused_group_qpsk16", "kernel_ms": kern_ms,
-                     "flops_per_vector": flops_vec},
+                   "t_max": T_MAX, "snr_db": SNR_TIMED, "alpha": ALPHA, "tau": "spectral",
+                   "precision": "bf16 MFMA products with fp32 accumulation; fp32 prox, norms, "
+                                "preconditioning and step size"},
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "quality": quality,
+        "paths": timing,
+        "accuracy": accuracy,
     }
     print(json.dumps(rec))
 

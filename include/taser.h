@@ -164,6 +164,20 @@ taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
                          int32_t* status, float* L_out, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* The two stages of taser_run, for callers that time or schedule them
+   separately.  taser_run_prep: T assembly, Jacobi preconditioning and the
+   step size (Section II, Section III-C), leaving each group's state in `ws`
+   and writing status [V].  taser_run_solve: t_max iterations of Algorithm 1
+   and slicing from that state; the descriptor must equal the one given to
+   taser_run_prep (except prec, which selects the product arithmetic) and the
+   workspace must be the same, untouched in between. */
+taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const void* y,
+                              const void* s0, const float* tau_in, int32_t* status, void* ws,
+                              size_t ws_bytes, void* stream);
+taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* margin,
+                               int32_t* status, float* L_out, void* ws, size_t ws_bytes,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

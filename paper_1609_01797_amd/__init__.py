@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
 
 LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -76,6 +76,10 @@ def load():
     lib.taser_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
     lib.taser_run.restype = ctypes.c_int
     lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.taser_run_prep.restype = ctypes.c_int
+    lib.taser_run_prep.argtypes = [D, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.taser_run_solve.restype = ctypes.c_int
+    lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     _lib = lib
     return lib
 
@@ -247,5 +251,65 @@ def run(desc: Desc, H, y, s0=None, tau=None, want_margin=False, want_L=False, ou
                        _opt(res.get("L") if want_L else None, torch.float32, V * N * (N + 1) // 2, "L"),
                        ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                        _stream(dev))
+    _raise(st)
+    return res
+
+
+def _outputs(desc, dev, res, want_margin, want_L):
+    torch = _torch()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    if "sbar" not in res:
+        res["sbar"] = torch.empty((V, N - 1), dtype=torch.int8, device=dev)
+    if "status" not in res:
+        res["status"] = torch.empty((V,), dtype=torch.int32, device=dev)
+    if want_margin and "margin" not in res:
+        res["margin"] = torch.empty((V, N - 1), dtype=torch.float32, device=dev)
+    if want_L and "L" not in res:
+        res["L"] = torch.empty((V, N * (N + 1) // 2), dtype=torch.float32, device=dev)
+    return res
+
+
+def _ws_for(desc, dev, ws):
+    torch = _torch()
+    nbytes = workspace_size(desc)
+    if ws is None:
+        ws = _workspace(nbytes, dev)
+    if ws.dtype != torch.uint8 or not ws.is_cuda or ws.numel() < nbytes:
+        raise ValueError(f"workspace must be a uint8 CUDA tensor of at least {nbytes} bytes")
+    return ws
+
+
+def run_prep(desc: Desc, H, y, s0=None, tau=None, out=None, ws=None):
+    """First stage of ``run``: T, preconditioning and step size into the
+    workspace; returns the ``out`` dict (status filled in)."""
+    torch = _torch()
+    lib = load()
+    V = desc.num_vectors
+    dev = y.device
+    ph, py, ps = _inputs(desc, H, y, s0)
+    pt = _need(tau, torch.float32, V, "tau") if desc.tau_mode == TAU_GIVEN else None
+    res = _outputs(desc, dev, out if out is not None else {}, False, False)
+    ws = _ws_for(desc, dev, ws)
+    st = lib.taser_run_prep(ctypes.byref(desc), ph, py, ps, pt,
+                            _need(res["status"], torch.int32, V, "status"),
+                            ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream(dev))
+    _raise(st)
+    return res
+
+
+def run_solve(desc: Desc, out, want_margin=False, want_L=False, ws=None, device=None):
+    """Second stage of ``run``: Algorithm 1 and slicing from the workspace the
+    matching ``run_prep`` filled."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    dev = device if device is not None else out["status"].device
+    res = _outputs(desc, dev, out, want_margin, want_L)
+    ws = _ws_for(desc, dev, ws)
+    st = lib.taser_run_solve(ctypes.byref(desc), _need(res["sbar"], torch.int8, V * (N - 1), "sbar"),
+                             _opt(res.get("margin") if want_margin else None, torch.float32, V * (N - 1), "margin"),
+                             _need(res["status"], torch.int32, V, "status"),
+                             _opt(res.get("L") if want_L else None, torch.float32, V * N * (N + 1) // 2, "L"),
+                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream(dev))
     _raise(st)
     return res

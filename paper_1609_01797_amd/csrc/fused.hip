@@ -383,6 +383,8 @@ __global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
   ws[kWsDN + lane] = DN;
   ws[kWsTau + lane] = tau;
   ws[kWsFlag + lane] = __int_as_float((nonfinite ? 2 : 0) | (degenerate ? 1 : 0));
+  if (g == 0 && a.status)
+    a.status[v] = nonfinite ? TASER_VEC_NONFINITE : (degenerate ? TASER_VEC_DEGENERATE : 0);
 }
 
 // Algorithm 1 for one channel group (one wave), from the state the prep
@@ -666,11 +668,13 @@ size_t fused_workspace_bytes(const FusedArgs& a) {
   return (size_t)(a.V / 16) * kWsFloats * sizeof(float);
 }
 
-hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
+hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(prep_group_qpsk16, dim3(a.V / 16), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s) {
   const int groups = a.V / 16;
-  hipLaunchKernelGGL(prep_group_qpsk16, dim3(groups), dim3(64), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (a.prec == TASER_PREC_BF16)
     hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_BF16>, dim3(groups), dim3(64), 0, s, a);
   else if (a.prec == TASER_PREC_F16)
@@ -678,6 +682,12 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_F32>, dim3(groups), dim3(64), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
+  hipError_t e = launch_fused_prep(a, s);
+  if (e != hipSuccess) return e;
+  return launch_fused_solve(a, s);
 }
 
 }  // namespace taser

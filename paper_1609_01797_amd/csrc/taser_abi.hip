@@ -158,4 +158,43 @@ taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
                                                                         : TASER_ERR_DEVICE;
 }
 
+taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const void* y,
+                              const void* s0, const float* tau_in, int32_t* status, void* ws,
+                              size_t ws_bytes, void* stream) {
+  FusedArgs a;
+  taser_status_t st = fused_args(desc, &a);
+  if (st != TASER_OK) return st;
+  if (a.V == 0) return TASER_OK;
+  const bool jed = desc->mode == TASER_JED;
+  if (!y || !status) return TASER_ERR_ARG;
+  if (!jed && !H) return TASER_ERR_ARG;
+  if (jed && !s0) return TASER_ERR_ARG;
+  if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
+  const size_t need = fused_workspace_bytes(a);
+  if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
+  a.H = static_cast<const float2*>(H);
+  a.y = static_cast<const float2*>(y);
+  a.s0 = static_cast<const float2*>(s0);
+  a.tau_in = tau_in; a.status = status;
+  a.ws = static_cast<float*>(ws);
+  return launch_fused_prep(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
+                                                                             : TASER_ERR_DEVICE;
+}
+
+taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* margin,
+                               int32_t* status, float* L_out, void* ws, size_t ws_bytes,
+                               void* stream) {
+  FusedArgs a;
+  taser_status_t st = fused_args(desc, &a);
+  if (st != TASER_OK) return st;
+  if (a.V == 0) return TASER_OK;
+  if (!sbar || !status) return TASER_ERR_ARG;
+  const size_t need = fused_workspace_bytes(a);
+  if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
+  a.sbar = sbar; a.margin = margin; a.status = status; a.L_out = L_out;
+  a.ws = static_cast<float*>(ws);
+  return launch_fused_solve(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
+                                                                              : TASER_ERR_DEVICE;
+}
+
 }  // extern "C"

@@ -48,6 +48,8 @@ struct FusedArgs {
 bool fused_supported(const FusedArgs& a);
 size_t fused_workspace_bytes(const FusedArgs& a);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
+hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
+hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s);
 
 // LDS bytes the staged build kernel needs (0 if the shape does not fit).
 size_t build_T_lds_bytes(int B, int U, int N);

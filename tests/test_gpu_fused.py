@@ -108,8 +108,53 @@ def test_fused_ragged_and_flags(gpu_lib, Bx, t_max, flags):
 
 
 def test_fused_rejects_unsupported(gpu_lib):
+    """Shapes outside the fused kernel (here U = 8, one vector per H) are refused."""
     import torch
     desc = gpu_lib.make_desc(64, 32, 8, oracle.QPSK, y_per_H=1, t_max=10)
     with pytest.raises(gpu_lib.TaserError):
         gpu_lib.run(desc, torch.zeros((64, 32, 8), dtype=torch.complex64, device="cuda"),
                     torch.zeros((64, 32), dtype=torch.complex64, device="cuda"))
+
+
+# 16-bit products: operands rounded to BF16 (unit roundoff 2^-8) or FP16
+# (2^-11), products accumulated and the prox computed in float32.  Over ten
+# iterations the relative error of L~ stays within a few unit roundoffs of the
+# operand format; the tolerances are 2.5 u (BF16) and 4 u (FP16).  Decisions may
+# differ only where the oracle's margin is within the margin error the
+# rounding allows (10 u).
+PREC_TOL = {1: (2.5 * 2.0 ** -8, 10 * 2.0 ** -8), 2: (4 * 2.0 ** -11, 10 * 2.0 ** -11)}
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("snr", [0.0, 4.0, 12.0])
+def test_fused_16bit_products(gpu_lib, prec, snr):
+    d = sim.gen_mimo(B, U, oracle.QPSK, 64, YPH, snr, sim.seed_for(2, snr_index=int(snr) + 20, shard=prec))
+    ref = _group_oracle(d, 0.5, 10)
+    desc = gpu_lib.make_desc(1024, B, U, oracle.QPSK, prec=prec, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=YPH,
+                             t_max=10)
+    g = fused(gpu_lib, desc, d["H"], d["y"], tau=ref["tau"].astype(np.float32))
+    ltol, mtol = PREC_TOL[prec]
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"], tol=ltol)
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=mtol)
+    np.testing.assert_array_equal(g["status"], ref["status"])
+
+
+def test_fused_prep_then_solve_equals_run(gpu_lib):
+    """taser_run_prep + taser_run_solve give exactly what taser_run gives, and
+    one prep can feed solves of different product precisions."""
+    import torch
+    d = sim.gen_mimo(B, U, oracle.QPSK, 32, YPH, 3.0, 4343)
+    H, y = _cuda(d["H"]), _cuda(d["y"])
+    desc = gpu_lib.make_desc(512, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=0.5)
+    ref = gpu_lib.run(desc, H, y, want_margin=True, want_L=True)
+    ws = torch.empty(gpu_lib.workspace_size(desc), dtype=torch.uint8, device="cuda")
+    out = gpu_lib.run_prep(desc, H, y, ws=ws)
+    out = gpu_lib.run_solve(desc, out, want_margin=True, want_L=True, ws=ws)
+    torch.cuda.synchronize()
+    for k in ("sbar", "status", "margin", "L"):
+        assert torch.equal(out[k], ref[k]), k
+    desc16 = gpu_lib.make_desc(512, B, U, oracle.QPSK, prec=gpu_lib.PREC_F16, y_per_H=YPH, t_max=10, alpha=0.5)
+    ref16 = gpu_lib.run(desc16, H, y, want_L=True)
+    out16 = gpu_lib.run_solve(desc16, {"status": out["status"].clone()}, want_L=True, ws=ws, device=H.device)
+    torch.cuda.synchronize()
+    assert torch.equal(out16["L"], ref16["L"]) and torch.equal(out16["sbar"], ref16["sbar"])
