@@ -659,13 +659,17 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
 
 }  // namespace
 
-bool fused_supported(const FusedArgs& a) {
+bool fused_group_supported(const FusedArgs& a) {
   return a.mode == TASER_COHERENT && a.mod == TASER_QPSK && a.U == 16 && a.y_per_H % 16 == 0 &&
          a.B >= 1;
 }
 
+bool fused_supported(const FusedArgs& a) {
+  return fused_group_supported(a) || fused_vec_tiles(a) > 0;
+}
+
 size_t fused_workspace_bytes(const FusedArgs& a) {
-  return (size_t)(a.V / 16) * kWsFloats * sizeof(float);
+  return fused_group_supported(a) ? (size_t)(a.V / 16) * kWsFloats * sizeof(float) : 0;
 }
 
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s) {
@@ -685,6 +689,7 @@ hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s) {
+  if (!fused_group_supported(a)) return launch_fused_vec(a, s);
   hipError_t e = launch_fused_prep(a, s);
   if (e != hipSuccess) return e;
   return launch_fused_solve(a, s);

@@ -1,0 +1,639 @@
+// Fused single-launch TASER for vectors that each have their own T~:
+// coherent detection with one channel per vector (or per few vectors) and
+// joint channel estimation and detection (Section II-B), BPSK or QPSK, for
+// N - 1 <= 16 NT with NT in {1, 2, 4} (padded problems keep their padded
+// rows and columns at zero).
+//
+// One wave detects one vector.  T~ is bordered, T~ = [G~ c~; c~^T t], with
+// G~ the (N-1)x(N-1) block.  The L~ T~ product of Algorithm 1 runs on
+// 16x16x4 MFMAs with G~ as the A operand (held in NT*NT*4 VGPRs) and a
+// 16-row tile of L~ as the B operand: lane l serves row (l % 16) of a row
+// tile and column quad g = l / 16, holding columns 16 jt + 4 r + g in
+// register (jt, r); the output rows are permuted by jj(m) = 4 (m % 4) + m/4
+// so that the product lands in the same layout.  Column norms are sums over
+// the 16 rows of each tile (DPP within a 16-lane row).  The last row of L~
+// and the Lanczos vectors of the step-size estimate are handled as
+// matrix-vector products through the same A registers on the vector ALUs.
+#include <math.h>
+
+#include <type_traits>
+
+#include "taser_internal.h"
+
+namespace taser {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (Begin < End) {
+    f(std::integral_constant<int, Begin>{});
+    sfor<Begin + 1, End>(f);
+  }
+}
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int P>
+__device__ __forceinline__ unsigned cvt_pk(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 x = {lo, hi};
+  if constexpr (P == TASER_PREC_BF16) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(x, b2));
+  } else {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(x, h2));
+  }
+}
+
+template <int P>
+__device__ __forceinline__ u2 pack4(float x0, float x1, float x2, float x3) {
+  return u2{cvt_pk<P>(x0, x1), cvt_pk<P>(x2, x3)};
+}
+
+template <int P>
+__device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
+  if constexpr (P == TASER_PREC_BF16)
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a),
+                                                     __builtin_bit_cast(s4, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4, a),
+                                                 __builtin_bit_cast(h4, b), c, 0, 0, 0);
+}
+
+// Sum over the four column quads (lanes n, n+16, n+32, n+48).
+__device__ __forceinline__ float sum_quads(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const unsigned w = __float_as_uint(y);
+  const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the 16 lanes of each 16-lane row (the rows of a tile), by
+// rotations inside the row (DPP row_ror).
+__device__ __forceinline__ float sum_rows16(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, false));
+  return x;
+}
+
+__device__ __forceinline__ int or_all(int x) {
+  return __ballot(x != 0) != 0ull;
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+constexpr int kLanczos = 12;
+
+// Largest eigenvalue of the symmetric tridiagonal (al, b2 = beta^2), the same
+// in every lane, by 65-way multisection: in each round lane l tests the
+// point lo + (l + 1)(hi - lo)/65 with a Sturm count (the number of
+// eigenvalues below it).  Plain float32 Lanczos repeats converged Ritz values
+// (loss of orthogonality), and counting is insensitive to such clusters.
+// The bracket is [max_k al_k, Gershgorin upper bound]: diagonal entries are
+// Rayleigh quotients, so the largest one bounds the top eigenvalue below.
+template <int M>
+__device__ __forceinline__ float top_eigenvalue(const float (&al)[M], const float (&b2)[M]) {
+  float lo = -3.4e38f, hi = -3.4e38f;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const float rad = (k > 0 ? sqrtf(b2[k - 1]) : 0.f) + (k < M - 1 ? sqrtf(b2[k]) : 0.f);
+    hi = fmaxf(hi, al[k] + rad);
+    lo = fmaxf(lo, al[k]);
+  }
+  const float pivmin = 1e-30f + 1e-12f * fabsf(hi);
+  const int lane = threadIdx.x & 63;
+  for (int round = 0; round < 5; ++round) {
+    const float w = (hi - lo) * (1.f / 65.f);
+    const float x = lo + w * (float)(lane + 1);
+    int cnt = 0;
+    float d = al[0] - x;
+    if (fabsf(d) < pivmin) d = -pivmin;
+    cnt += d < 0.f;
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+      d = (al[k] - x) - b2[k - 1] * rcp(d);
+      if (fabsf(d) < pivmin) d = -pivmin;
+      cnt += d < 0.f;
+    }
+    const unsigned long long hit = __ballot(cnt >= M);   // every eigenvalue below x
+    const int first = hit ? __ffsll((long long)hit) - 1 : 64;
+    const float nlo = lo + w * (float)first;
+    hi = first < 64 ? lo + w * (float)(first + 1) : hi;
+    lo = nlo;
+    if (!(hi - lo > 0.f)) break;
+  }
+  return 0.5f * (lo + hi);
+}
+
+// Largest number of T entries a lane accumulates: U(U+1)/2 Gram pairs, U
+// matched-filter entries and ||y||^2, spread over 64 lanes, for U <= 32.
+constexpr int kEntriesPerLane = 9;
+constexpr int kChunk = 32;   // channel rows staged in LDS per pass
+
+template <int NT>
+struct VecLds {
+  static constexpr int N1 = 16 * NT;
+  static constexpr int UMAX = N1 < 32 ? N1 : 32;                 // largest U for this tile count
+  static constexpr int TT = (N1 + 1) * (N1 + 1);                 // padded T
+  static constexpr int STAGE = kChunk * (UMAX + 1) * 2;          // rows x (U + y) complex
+  static constexpr int REGION = TT > STAGE ? TT : STAGE;
+  static constexpr int FLOATS = REGION + (N1 + 1) + N1;          // + D + shuffle buffer
+};
+
+template <int NT, int P>
+__global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
+  constexpr int N1 = 16 * NT;
+  using S = VecLds<NT>;
+  __shared__ __align__(16) float lds[S::FLOATS];
+  float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
+  float2* stage = reinterpret_cast<float2*>(lds);  // aliases T while the Gram is accumulated
+  float* Dl = lds + S::REGION;           // [N1+1]
+  float* sh = Dl + (N1 + 1);             // [N1] layout shuffle
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15;
+  const int g = lane >> 4;
+  const long long v = blockIdx.x;
+  const int B = a.B, U = a.U, Nm1 = a.N - 1;
+  const bool jed = a.mode == TASER_JED;
+  const bool qpsk = a.mod == TASER_QPSK;
+  const float sg = jed ? -1.f : 1.f;
+
+  // ---------------- preprocessing: complex Gram, H^H y, ||y||^2 ----------------
+  const int n_pairs = U * (U + 1) / 2;
+  const int n_entries = n_pairs + U + 1;
+  int ep[kEntriesPerLane], eq[kEntriesPerLane];
+#pragma unroll
+  for (int k = 0; k < kEntriesPerLane; ++k) {
+    const int e = lane + 64 * k;
+    int p = -1, q = -1;
+    if (e < n_pairs) {
+      p = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+      while (p * (p + 1) / 2 > e) --p;
+      while ((p + 1) * (p + 2) / 2 <= e) ++p;
+      q = e - p * (p + 1) / 2;
+    } else if (e < n_pairs + U) {
+      p = e - n_pairs;
+      q = U;                                   // column U of the stage = y
+    } else if (e < n_entries) {
+      p = U;
+      q = U;
+    }
+    ep[k] = p;
+    eq[k] = q;
+  }
+  float are[kEntriesPerLane], aim[kEntriesPerLane];
+#pragma unroll
+  for (int k = 0; k < kEntriesPerLane; ++k) { are[k] = 0.f; aim[k] = 0.f; }
+  const int W = U + 1;                         // stage row width (complex)
+  const float2* Hg = jed ? nullptr : a.H + (v / a.y_per_H) * (long long)B * U;
+  const float2* yg = jed ? a.y + v * (long long)(U + 1) * B : a.y + v * (long long)B;
+  float2 s0 = make_float2(1.f, 0.f);
+  if (jed) s0 = a.s0[v];
+  for (int b0 = 0; b0 < B; b0 += kChunk) {
+    const int rows = min(kChunk, B - b0);
+    for (int e = lane; e < rows * W; e += 64) {
+      const int r = e / W, c = e - r * W;
+      const int b = b0 + r;
+      float2 x;
+      if (!jed) {
+        x = c < U ? Hg[(long long)b * U + c] : yg[b];
+      } else if (c < U) {
+        x = yg[(long long)(c + 1) * B + b];    // Y_r: slots 1..K
+      } else {
+        const float2 y0 = yg[b];                // y_0 s_0
+        x = make_float2(y0.x * s0.x - y0.y * s0.y, y0.x * s0.y + y0.y * s0.x);
+      }
+      stage[r * W + c] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kEntriesPerLane; ++k) {
+      if (ep[k] >= 0) {
+        float re = are[k], im = aim[k];
+#pragma unroll 2
+        for (int r = 0; r < rows; ++r) {
+          const float2 hp = stage[r * W + ep[k]];
+          const float2 hq = stage[r * W + eq[k]];
+          re += hp.x * hq.x + hp.y * hq.y;     // conj(h_p) h_q
+          im += hp.x * hq.y - hp.y * hq.x;
+        }
+        are[k] = re;
+        aim[k] = im;
+      }
+    }
+    __syncthreads();
+  }
+  // T in padded indexing (eq. (2) coherent, eq. (5) joint detection)
+  for (int e = lane; e < S::TT; e += 64) T[e] = 0.f;
+  __syncthreads();
+  constexpr int LD = N1 + 1;
+#pragma unroll
+  for (int k = 0; k < kEntriesPerLane; ++k) {
+    const int p = ep[k], q = eq[k];
+    if (p < 0) continue;
+    if (p < U && q < U) {
+      const float gre = sg * are[k], gim = sg * aim[k];
+      if (qpsk) {
+        T[p * LD + q] = gre; T[q * LD + p] = gre;
+        T[(U + p) * LD + U + q] = gre; T[(U + q) * LD + U + p] = gre;
+        T[p * LD + U + q] = -gim; T[(U + q) * LD + p] = -gim;
+        if (p != q) { T[q * LD + U + p] = gim; T[(U + p) * LD + q] = gim; }
+      } else {
+        T[p * LD + q] = gre; T[q * LD + p] = gre;
+      }
+    } else if (p < U) {
+      // last column: -Hbar^T ybar in both modes
+      T[p * LD + N1] = -are[k]; T[N1 * LD + p] = -are[k];
+      if (qpsk) { T[(U + p) * LD + N1] = -aim[k]; T[N1 * LD + U + p] = -aim[k]; }
+    } else {
+      T[N1 * LD + N1] = sg * are[k];
+    }
+  }
+  __syncthreads();
+
+  // ---------------- Jacobi preconditioning (Section III-C) ----------------
+  int bad = 0, deg = 0;
+  for (int e = lane; e < S::TT; e += 64)
+    if (!isfinite(T[e])) bad = 1;
+  const bool nonfinite = or_all(bad);
+  for (int k = lane; k <= N1; k += 64) {
+    const bool real_k = k < Nm1 || k == N1;
+    const float d = nonfinite ? 0.f : fabsf(T[k * LD + k]);
+    if (real_k && d == 0.f) deg = 1;
+    Dl[k] = (d == 0.f || !real_k) ? 1.f : sqrtf(d);
+  }
+  const bool degenerate = !nonfinite && or_all(deg);
+  const bool skip = nonfinite || degenerate;
+  __syncthreads();
+  const float DN = Dl[N1];
+  const float tNN = skip ? 0.f : T[N1 * LD + N1] / (DN * DN);
+  float A[NT][NT][4];
+  {
+    const int jr = 4 * (n & 3) + (n >> 2);
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+      const int j = 16 * JT + jr;
+      const float dj = Dl[j];
+      sfor<0, NT>([&](auto kc) {
+        constexpr int KT = decltype(kc)::value;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = 16 * KT + 4 * s + g;
+          A[JT][KT][s] = skip ? 0.f : T[j * LD + k] / (dj * Dl[k]);
+        }
+      });
+    });
+  }
+  float ct[NT][4], Dc[NT][4];
+  bool act[NT][4];
+  sfor<0, NT>([&](auto jc) {
+    constexpr int JT = decltype(jc)::value;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * JT + 4 * r + g;
+      act[JT][r] = j < Nm1;
+      Dc[JT][r] = Dl[j];
+      ct[JT][r] = skip ? 0.f : T[j * LD + N1] / (Dl[j] * DN);
+    }
+  });
+  __syncthreads();   // T is dead from here on; sh may be reused freely
+
+  // w (row layout, index 16 jt + jj(m) in lane (m, p)) = G~ x, with x in
+  // column layout; returned in column layout through the LDS shuffle.
+  auto gemv = [&](const float (&x)[NT][4], float (&w)[NT][4]) {
+    const int jr = 4 * (n & 3) + (n >> 2);
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+      float part = 0.f;
+      sfor<0, NT>([&](auto kc) {
+        constexpr int KT = decltype(kc)::value;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) part = fmaf(A[JT][KT][s], x[KT][s], part);
+      });
+      part = sum_quads(part);
+      if (g == 0) sh[16 * JT + jr] = part;
+    });
+    // one wave: its LDS accesses complete in program order; the barrier keeps
+    // the compiler from moving them across
+    __builtin_amdgcn_wave_barrier();
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[JT][r] = sh[16 * JT + 4 * r + g];
+    });
+    __builtin_amdgcn_wave_barrier();
+  };
+  auto dot = [&](const float (&x)[NT][4], const float (&y)[NT][4]) {
+    float s = 0.f;
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s = fmaf(x[JT][r], y[JT][r], s);
+    });
+    return sum_quads(s);
+  };
+
+  // ---------------- step size tau = alpha / ||T~||_2 ----------------
+  float tau;
+  if (a.tau_mode == TASER_TAU_GIVEN) {
+    tau = a.tau_in[v];
+  } else {
+    // Lanczos on sg*T~ (positive semidefinite in both modes) from T~ e_N.
+    float al[kLanczos], b2[kLanczos];
+    float Q[NT][4], Qp[NT][4], Wv[NT][4];
+    float q32 = sg * tNN, qp32 = 0.f, beta = 0.f;
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { Q[JT][r] = sg * ct[JT][r]; Qp[JT][r] = 0.f; }
+    });
+    const float nrm = dot(Q, Q) + q32 * q32;
+    const float inv0 = nrm > 0.f ? rsqrtf(nrm) : 0.f;
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Q[JT][r] *= inv0;
+    });
+    q32 *= inv0;
+    bool done = false;
+    float scale = 0.f;
+    sfor<0, kLanczos>([&](auto jc) {
+      constexpr int J = decltype(jc)::value;
+      gemv(Q, Wv);
+      sfor<0, NT>([&](auto tc) {
+        constexpr int JT = decltype(tc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wv[JT][r] = sg * (Wv[JT][r] + ct[JT][r] * q32);
+      });
+      float w32 = sg * (dot(ct, Q) + tNN * q32);
+      const float alj = dot(Wv, Q) + w32 * q32;
+      sfor<0, NT>([&](auto tc) {
+        constexpr int JT = decltype(tc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wv[JT][r] -= alj * Q[JT][r] + beta * Qp[JT][r];
+      });
+      w32 -= alj * q32 + beta * qp32;
+      const float bb = dot(Wv, Wv) + w32 * w32;
+      if (!done) {
+        al[J] = alj;
+        b2[J] = bb;
+        scale = fmaxf(scale, fabsf(alj));
+        if (!(bb > 1e-12f * scale * scale)) { done = true; b2[J] = 0.f; }
+      } else {
+        al[J] = -1e30f;
+        b2[J] = 0.f;
+      }
+      beta = sqrtf(bb);
+      const float ib = beta > 0.f ? rcp(beta) : 0.f;
+      sfor<0, NT>([&](auto tc) {
+        constexpr int JT = decltype(tc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { Qp[JT][r] = Q[JT][r]; Q[JT][r] = Wv[JT][r] * ib; }
+      });
+      qp32 = q32;
+      q32 = w32 * ib;
+    });
+    const float lam = top_eigenvalue<kLanczos>(al, b2);
+    tau = a.alpha / (lam > 0.f ? lam : 1.f);
+  }
+  const float m2tau = -2.f * tau;
+
+  // ---------------- Algorithm 1 ----------------
+  constexpr bool k16 = P != TASER_PREC_F32;
+  u2 Ah[NT][NT];
+  if constexpr (k16) {
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+      sfor<0, NT>([&](auto kc) {
+        constexpr int KT = decltype(kc)::value;
+        Ah[JT][KT] = pack4<P>(A[JT][KT][0], A[JT][KT][1], A[JT][KT][2], A[JT][KT][3]);
+      });
+    });
+  }
+  // Lt[it][jt][r]: row 16 it + n, column 16 jt + 4 r + g (jt <= it)
+  float Lt[NT][NT][4];
+  float l21[NT][4];
+  float l22 = DN;
+  sfor<0, NT>([&](auto ic) {
+    constexpr int IT = decltype(ic)::value;
+    sfor<0, IT + 1>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Lt[IT][JT][r] = (IT == JT && n == 4 * r + g && act[JT][r]) ? Dc[JT][r] : 0.f;
+    });
+  });
+  sfor<0, NT>([&](auto jc) {
+    constexpr int JT = decltype(jc)::value;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) l21[JT][r] = 0.f;
+  });
+  const bool pin = !(a.flags & TASER_FLAG_LITERAL_LAST);
+  int st_bits = 0;
+  const int iters = skip ? 0 : a.t_max;
+  for (int t = 0; t < iters; ++t) {
+    // last row first (its product reads the old l21)
+    float lw[NT][4];
+    gemv(l21, lw);
+    const float cl = dot(l21, ct);
+    float nsq[NT][4];
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) nsq[JT][r] = 0.f;
+    });
+    // L11 tiles: V = L~ - 2 tau tril(L~ T~)
+    sfor<0, NT>([&](auto ic) {
+      constexpr int IT = decltype(ic)::value;
+      f4 acc[IT + 1];
+      if constexpr (k16) {
+        u2 bk[IT + 1];
+        sfor<0, IT + 1>([&](auto kc) {
+          constexpr int KT = decltype(kc)::value;
+          bk[KT] = pack4<P>(Lt[IT][KT][0], Lt[IT][KT][1], Lt[IT][KT][2], Lt[IT][KT][3]);
+        });
+        sfor<0, IT + 1>([&](auto jc) {
+          constexpr int JT = decltype(jc)::value;
+          acc[JT] = f4{0.f, 0.f, 0.f, 0.f};
+          sfor<0, IT + 1>([&](auto kc) {
+            constexpr int KT = decltype(kc)::value;
+            acc[JT] = mfma16<P>(Ah[JT][KT], bk[KT], acc[JT]);
+          });
+        });
+      } else {
+        sfor<0, IT + 1>([&](auto jc) {
+          constexpr int JT = decltype(jc)::value;
+          acc[JT] = f4{0.f, 0.f, 0.f, 0.f};
+          sfor<0, IT + 1>([&](auto kc) {
+            constexpr int KT = decltype(kc)::value;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[JT] = mfma(A[JT][KT][s], Lt[IT][KT][s], acc[JT]);
+          });
+        });
+      }
+      sfor<0, IT + 1>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float x = fmaf(m2tau, acc[JT][r], Lt[IT][JT][r]);
+          if (IT == JT && 4 * r + g > n) x = 0.f;   // strictly upper part
+          Lt[IT][JT][r] = x;
+          nsq[JT][r] = fmaf(x, x, nsq[JT][r]);
+        }
+      });
+    });
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float x = fmaf(m2tau, fmaf(l22, ct[JT][r], lw[JT][r]), l21[JT][r]);
+        l21[JT][r] = x;
+        nsq[JT][r] = sum_rows16(nsq[JT][r]) + x * x;
+      }
+    });
+    const float vnn = fmaf(m2tau, fmaf(l22, tNN, cl), l22);
+    if (!(vnn > 0.f)) st_bits |= TASER_VEC_VNN_NONPOS;
+    // prox: column j <- D_j V_:,j / ||V_:,j||
+    float sc[NT][4];
+    int any_bad = 0;
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float q = nsq[JT][r];
+        const bool ok = q > 0.f && q < 3.4e38f;
+        sc[JT][r] = (ok && act[JT][r]) ? Dc[JT][r] * __builtin_amdgcn_rsqf(q) : 0.f;
+        any_bad |= (!ok && act[JT][r]);
+      }
+    });
+    sfor<0, NT>([&](auto ic) {
+      constexpr int IT = decltype(ic)::value;
+      sfor<0, IT + 1>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Lt[IT][JT][r] *= sc[JT][r];
+      });
+    });
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) l21[JT][r] *= sc[JT][r];
+    });
+    if (__builtin_expect(__ballot(any_bad) != 0ull, 0)) {
+      // columns with zero / non-finite norm restart from D_jj e_j
+      st_bits |= TASER_VEC_ZERO_NORM;
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (act[JT][r] && sc[JT][r] == 0.f && n == 4 * r + g) Lt[JT][JT][r] = Dc[JT][r];
+      });
+    }
+    if (pin) {
+      l22 = DN;
+    } else if (vnn != 0.f && isfinite(vnn)) {
+      l22 = vnn > 0.f ? DN : -DN;
+    } else {
+      l22 = DN;
+      st_bits |= TASER_VEC_ZERO_NORM;
+    }
+  }
+
+  // ---------------- slicing and outputs ----------------
+  const int bits = skip ? (nonfinite ? TASER_VEC_NONFINITE : TASER_VEC_DEGENERATE) : st_bits;
+  if (lane == 0) a.status[v] = bits;
+  if (n == 0) {
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * JT + 4 * r + g;
+        if (j < Nm1) {
+          const float x = skip ? 0.f : l21[JT][r];
+          a.sbar[v * Nm1 + j] = x >= 0.f ? (int8_t)1 : (int8_t)-1;
+          if (a.margin) a.margin[v * Nm1 + j] = skip ? 0.f : x / Dc[JT][r];
+        }
+      }
+    });
+  }
+  if (a.L_out) {
+    const int Nn = Nm1 + 1;
+    float* Lo = a.L_out + v * (long long)(Nn * (Nn + 1) / 2);
+    sfor<0, NT>([&](auto ic) {
+      constexpr int IT = decltype(ic)::value;
+      sfor<0, IT + 1>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * IT + n, j = 16 * JT + 4 * r + g;
+          if (i < Nm1 && j <= i) {
+            float x = Lt[IT][JT][r];
+            if (skip) x = (i == j) ? Dc[JT][r] : 0.f;
+            Lo[i * (i + 1) / 2 + j] = x;
+          }
+        }
+      });
+    });
+    if (n == 0) {
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * JT + 4 * r + g;
+          if (j < Nm1) Lo[Nm1 * (Nm1 + 1) / 2 + j] = skip ? 0.f : l21[JT][r];
+        }
+      });
+    }
+    if (lane == 0) Lo[Nm1 * (Nm1 + 1) / 2 + Nm1] = skip ? DN : l22;
+  }
+}
+
+template <int NT>
+bool launch_vec_nt(const FusedArgs& a, hipStream_t s) {
+  const dim3 grid(a.V), block(64);
+  if (a.prec == TASER_PREC_BF16)
+    hipLaunchKernelGGL((fused_vec<NT, TASER_PREC_BF16>), grid, block, 0, s, a);
+  else if (a.prec == TASER_PREC_F16)
+    hipLaunchKernelGGL((fused_vec<NT, TASER_PREC_F16>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((fused_vec<NT, TASER_PREC_F32>), grid, block, 0, s, a);
+  return true;
+}
+
+}  // namespace
+
+int fused_vec_tiles(const FusedArgs& a) {
+  const int nm1 = a.N - 1;
+  if (a.U > 32) return 0;                       // Gram entries per lane and staging bound
+  if (a.B < 1) return 0;
+  if (a.mode == TASER_JED && a.y_per_H != 1) return 0;
+  if (nm1 <= 16) return 1;
+  if (nm1 <= 32) return 2;
+  if (nm1 <= 64) return 4;
+  return 0;
+}
+
+hipError_t launch_fused_vec(const FusedArgs& a, hipStream_t s) {
+  switch (fused_vec_tiles(a)) {
+    case 1: launch_vec_nt<1>(a, s); break;
+    case 2: launch_vec_nt<2>(a, s); break;
+    case 4: launch_vec_nt<4>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace taser

@@ -164,6 +164,7 @@ taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const voi
   FusedArgs a;
   taser_status_t st = fused_args(desc, &a);
   if (st != TASER_OK) return st;
+  if (!fused_group_supported(a)) return TASER_ERR_UNSUPPORTED;
   if (a.V == 0) return TASER_OK;
   const bool jed = desc->mode == TASER_JED;
   if (!y || !status) return TASER_ERR_ARG;
@@ -187,6 +188,7 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
   FusedArgs a;
   taser_status_t st = fused_args(desc, &a);
   if (st != TASER_OK) return st;
+  if (!fused_group_supported(a)) return TASER_ERR_UNSUPPORTED;
   if (a.V == 0) return TASER_OK;
   if (!sbar || !status) return TASER_ERR_ARG;
   const size_t need = fused_workspace_bytes(a);

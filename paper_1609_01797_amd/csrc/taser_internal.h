@@ -45,7 +45,10 @@ struct FusedArgs {
   float* L_out;
   float* ws;           // workspace, fused_workspace_bytes(a) bytes
 };
-bool fused_supported(const FusedArgs& a);
+bool fused_supported(const FusedArgs& a);        // group or per-vector kernel applies
+bool fused_group_supported(const FusedArgs& a);  // 16 vectors share one channel (two kernels)
+int fused_vec_tiles(const FusedArgs& a);         // per-vector kernel tile count, 0 = no
+hipError_t launch_fused_vec(const FusedArgs& a, hipStream_t s);
 size_t fused_workspace_bytes(const FusedArgs& a);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);

@@ -98,8 +98,10 @@ def test_workspace_size_query():
     assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
     assert n.value == 4096 * 2048 * 4
     assert lib.taser_workspace_size(ctypes.byref(d), None) == taser.ERR_ARG
-    other = taser.make_desc(64, 32, 8, taser.QPSK)
-    assert lib.taser_workspace_size(ctypes.byref(other), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
+    other = taser.make_desc(64, 32, 8, taser.QPSK)      # per-vector kernel: no workspace
+    assert lib.taser_workspace_size(ctypes.byref(other), ctypes.byref(n)) == taser.OK and n.value == 0
+    big = taser.make_desc(4, 64, 40, taser.QPSK)        # N = 81: no fused kernel
+    assert lib.taser_workspace_size(ctypes.byref(big), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
     # a run with a missing workspace is rejected before any launch
     z = ctypes.c_void_p(0)
     one = ctypes.c_void_p(16)   # non-null but never dereferenced: the call fails first

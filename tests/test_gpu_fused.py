@@ -108,12 +108,13 @@ def test_fused_ragged_and_flags(gpu_lib, Bx, t_max, flags):
 
 
 def test_fused_rejects_unsupported(gpu_lib):
-    """Shapes outside the fused kernel (here U = 8, one vector per H) are refused."""
+    """Problems beyond the fused kernels (N - 1 > 64, or more than 32 users)
+    are refused; the staged calls cover them."""
     import torch
-    desc = gpu_lib.make_desc(64, 32, 8, oracle.QPSK, y_per_H=1, t_max=10)
+    desc = gpu_lib.make_desc(4, 64, 40, oracle.QPSK, y_per_H=1, t_max=10)
     with pytest.raises(gpu_lib.TaserError):
-        gpu_lib.run(desc, torch.zeros((64, 32, 8), dtype=torch.complex64, device="cuda"),
-                    torch.zeros((64, 32), dtype=torch.complex64, device="cuda"))
+        gpu_lib.run(desc, torch.zeros((4, 64, 40), dtype=torch.complex64, device="cuda"),
+                    torch.zeros((4, 64), dtype=torch.complex64, device="cuda"))
 
 
 # 16-bit products: operands rounded to BF16 (unit roundoff 2^-8) or FP16

@@ -1,0 +1,132 @@
+"""Parity of the per-vector fused kernel (taser_run when vectors do not come
+in groups of 16 sharing a channel, and for joint channel estimation and
+detection) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import sim
+from parity import assert_L_parity, assert_decisions, unpack_lower
+
+pytestmark = pytest.mark.gpu
+
+PREC_TOL = {1: (2.5 * 2.0 ** -8, 10 * 2.0 ** -8), 2: (4 * 2.0 ** -11, 10 * 2.0 ** -11)}
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_fused(taser, desc, H=None, y=None, s0=None, tau=None):
+    import torch
+    res = taser.run(desc, None if H is None else _cuda(H), _cuda(y), None if s0 is None else _cuda(s0),
+                    tau=None if tau is None else _cuda(tau), want_margin=True, want_L=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+COHERENT = [
+    # (B, U, mod, num_H, y_per_H, snr, t_max, alpha)         N  tiles
+    (32, 8, oracle.QPSK, 1000, 1, 10.0, 10, 0.5),           # 17 1: the 32x8 parity workload
+    (32, 8, oracle.QPSK, 1000, 1, 10.0, 10, 0.9),
+    (64, 8, oracle.BPSK, 300, 1, 6.0, 10, 0.5),             # 9  1 (padded)
+    (128, 16, oracle.BPSK, 200, 1, 6.0, 10, 0.5),           # 17 1
+    (256, 32, oracle.BPSK, 60, 1, 8.0, 10, 0.5),            # 33 2
+    (256, 32, oracle.QPSK, 60, 1, 8.0, 10, 0.5),            # 65 4
+    (12, 5, oracle.QPSK, 131, 1, 3.0, 7, 0.7),              # 11 1 (ragged)
+    (100, 12, oracle.QPSK, 40, 4, 5.0, 10, 0.5),            # 25 2, 4 vectors per channel
+    (40, 30, oracle.QPSK, 30, 1, 15.0, 5, 0.6),             # 61 4 (overloaded-ish, padded)
+]
+
+
+@pytest.mark.parametrize("case", COHERENT, ids=lambda c: f"B{c[0]}U{c[1]}m{c[2]}V{c[3]*c[4]}a{c[7]}")
+def test_vec_coherent(gpu_lib, case):
+    B, U, mod, nH, yph, snr, t_max, alpha = case
+    d = sim.gen_mimo(B, U, mod, nH, yph, snr, sim.seed_for(3, shard=B + U + mod))
+    V = nH * yph
+    ref = oracle.detect_coherent(np.repeat(d["H"], yph, axis=0), d["y"], mod, alpha=alpha, t_max=t_max)
+    N = oracle.problem_size(U, mod)
+    # tau from the oracle: isolates the kernel from the eigenvalue estimate
+    desc = gpu_lib.make_desc(V, B, U, mod, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=yph, t_max=t_max)
+    g = run_fused(gpu_lib, desc, d["H"], d["y"], tau=ref["tau"].astype(np.float32))
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+    np.testing.assert_array_equal(g["status"], ref["status"])
+    # tau from the in-kernel Lanczos + Laguerre estimate
+    desc = gpu_lib.make_desc(V, B, U, mod, y_per_H=yph, t_max=t_max, alpha=alpha)
+    g = run_fused(gpu_lib, desc, d["H"], d["y"])
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
+JED = [(oracle.QPSK, 16, 16, 600, 20), (oracle.BPSK, 16, 8, 400, 20), (oracle.QPSK, 16, 3, 200, 5),
+       (oracle.BPSK, 8, 32, 100, 12), (oracle.QPSK, 24, 30, 50, 10)]
+
+
+@pytest.mark.parametrize("mod,Bx,K,nb,t_max", JED, ids=lambda x: str(x))
+def test_vec_jed(gpu_lib, mod, Bx, K, nb, t_max):
+    d = sim.gen_jed(Bx, K, mod, nb, 6.0, sim.seed_for(5, shard=K + Bx))
+    ref = oracle.detect_jed(d["Y"], d["s0"], mod, alpha=0.5, t_max=t_max)
+    N = oracle.problem_size(K, mod)
+    desc = gpu_lib.make_desc(nb, Bx, K, mod, mode=gpu_lib.JED, tau_mode=gpu_lib.TAU_GIVEN, t_max=t_max)
+    g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"], tau=ref["tau"].astype(np.float32))
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+    desc = gpu_lib.make_desc(nb, Bx, K, mod, mode=gpu_lib.JED, t_max=t_max, alpha=0.5)
+    g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"])
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+def test_vec_jed_16bit(gpu_lib, prec):
+    d = sim.gen_jed(16, 16, oracle.QPSK, 512, 4.0, sim.seed_for(5, shard=77 + prec))
+    ref = oracle.detect_jed(d["Y"], d["s0"], oracle.QPSK, alpha=0.5, t_max=20)
+    desc = gpu_lib.make_desc(512, 16, 16, oracle.QPSK, mode=gpu_lib.JED, prec=prec, tau_mode=gpu_lib.TAU_GIVEN,
+                             t_max=20)
+    g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"], tau=ref["tau"].astype(np.float32))
+    ltol, mtol = PREC_TOL[prec]
+    assert_L_parity(unpack_lower(g["L"], 33), ref["L"], tol=ltol)
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=mtol)
+
+
+def test_vec_degenerate_and_flags(gpu_lib):
+    B, U, mod = 32, 8, oracle.QPSK
+    d = sim.gen_mimo(B, U, mod, 8, 1, 5.0, 8181)
+    H, y = d["H"].copy(), d["y"].copy()
+    H[1, :, 3] = 0
+    y[2] = 0
+    y[3, 4] = np.nan
+    H[4, 7, 2] = np.inf
+    ref = oracle.detect_coherent(H, y, mod, alpha=0.5, t_max=6)
+    desc = gpu_lib.make_desc(8, B, U, mod, t_max=6, alpha=0.5)
+    g = run_fused(gpu_lib, desc, H, y)
+    np.testing.assert_array_equal(g["status"], ref["status"])
+    ok = ref["status"] == 0
+    assert_L_parity(unpack_lower(g["L"][ok], 17), ref["L"][ok])
+    assert np.all(g["sbar"][~ok] == 1) and np.all(g["margin"][~ok] == 0)
+    np.testing.assert_allclose(unpack_lower(g["L"][~ok], 17), ref["L"][~ok], rtol=1e-6)
+    # literal last column and t_max = 0
+    ref2 = oracle.detect_coherent(d["H"], d["y"], mod, alpha=0.95, t_max=5, pin_last=False)
+    desc2 = gpu_lib.make_desc(8, B, U, mod, tau_mode=gpu_lib.TAU_GIVEN, t_max=5, flags=gpu_lib.FLAG_LITERAL_LAST)
+    g2 = run_fused(gpu_lib, desc2, d["H"], d["y"], tau=ref2["tau"].astype(np.float32))
+    assert_L_parity(unpack_lower(g2["L"], 17), ref2["L"])
+    np.testing.assert_array_equal(g2["status"], ref2["status"])
+    desc0 = gpu_lib.make_desc(8, B, U, mod, t_max=0, alpha=0.5)
+    g0 = run_fused(gpu_lib, desc0, d["H"], d["y"])
+    assert np.all(g0["sbar"] == 1)
+
+
+def test_vec_zero_norm_reset(gpu_lib):
+    H = np.zeros((1, 4, 2), dtype=np.complex64)
+    H[0, 0, 0] = 1.0
+    H[0, 1, 1] = 1.0
+    y = np.zeros((1, 4), dtype=np.complex64)
+    y[0, 1] = 1.0 + 1.0j
+    y[0, 2] = 0.5
+    ref = oracle.detect_coherent(H, y, oracle.QPSK, tau=np.array([0.5]), t_max=1)
+    desc = gpu_lib.make_desc(1, 4, 2, oracle.QPSK, tau_mode=gpu_lib.TAU_GIVEN, t_max=1)
+    g = run_fused(gpu_lib, desc, H, y, tau=np.array([0.5], dtype=np.float32))
+    assert g["status"][0] & gpu_lib.VEC_ZERO_NORM
+    np.testing.assert_allclose(unpack_lower(g["L"], 5)[0], ref["L"][0], atol=1e-6)
