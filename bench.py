@@ -159,6 +159,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ber", action="store_true", help="skip the SNR sweep")
+    ap.add_argument("--workload", default="coherent128x16",
+                    choices=["coherent128x16", "jed16x16", "coherent32x8"],
+                    help="coherent128x16 (default, the headline), jed16x16 (joint channel "
+                         "estimation and detection, 262,144 blocks), coherent32x8 (1,000 vectors)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -177,6 +181,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+        return
+
+    if args.workload != "coherent128x16":
+        from bench_workloads import run_workload
+        print(json.dumps(run_workload(args)))
         return
 
     snrs = [SNR_TIMED] if args.no_ber else SNR_SWEEP

@@ -74,6 +74,7 @@ enum { TASER_TAU_SPECTRAL = 0,   /* tau = alpha / ||T~||_2 (Algorithm 1 inputs) 
 #define TASER_VEC_NONFINITE  2   /* NaN/Inf reached T: no iterations; L~ = D */
 #define TASER_VEC_ZERO_NORM  4   /* a prox column had zero norm and was reset */
 #define TASER_VEC_VNN_NONPOS 8   /* V_NN <= 0 occurred in some iteration */
+#define TASER_VEC_UNSUPPORTED 16 /* mixed batch: no fused kernel for this size; decisions +1 */
 
 typedef struct {
   int32_t num_vectors;  /* V >= 0: received vectors (coherent) or blocks (JED) */
@@ -176,6 +177,34 @@ taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const voi
                               size_t ws_bytes, void* stream);
 taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* margin,
                                int32_t* status, float* L_out, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* ---- Mixed-size batches ------------------------------------------------
+
+   Coherent detection of V vectors of different sizes in one call: vector v
+   has B_v receive antennas, U_v users and modulation mod_v, its own channel
+   (complex64 B_v x U_v row-major, starting H_off[v] complex elements into H)
+   and receive vector (B_v complex64 at y + y_off[v]).  The call sorts the
+   vectors into size buckets on the device (N-1 <= 16, <= 32, <= 64) and runs
+   one persistent kernel per bucket; it allocates nothing, synchronises
+   nothing and launches a fixed sequence of kernels (capturable into a HIP
+   graph).  desc->num_vectors, prec, tau_mode, t_max, flags and alpha apply to
+   every vector; desc->mode must be TASER_COHERENT; desc->B, U, mod and
+   y_per_H are not used.  Outputs: sbar int8 [V][stride] and margin float32
+   [V][stride] (or NULL): the first N_v - 1 entries of row v are the
+   decisions / margins, the rest of the row is 0; status [V].  Vectors with U_v > 32 or N_v - 1 > 64 get status
+   TASER_VEC_UNSUPPORTED.  All per-vector arrays are device arrays. */
+typedef struct {
+  int32_t blocks[3];    /* persistent blocks per bucket; 0 = library default */
+} taser_mixed_launch_t;
+
+taser_status_t taser_mixed_workspace_size(const taser_desc_t* desc, size_t* bytes);
+
+taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* B, const int32_t* U,
+                               const int32_t* mod, const int64_t* H_off, const int64_t* y_off,
+                               const void* H, const void* y, const float* tau_in, int8_t* sbar,
+                               float* margin, int32_t stride, int32_t* status,
+                               const taser_mixed_launch_t* launch, void* ws, size_t ws_bytes,
                                void* stream);
 
 #ifdef __cplusplus

@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
 
 LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -27,7 +27,7 @@ COHERENT, JED = 0, 1
 PREC_F32, PREC_BF16, PREC_F16 = 0, 1, 2
 TAU_SPECTRAL, TAU_GIVEN = 0, 1
 FLAG_LITERAL_LAST = 1
-VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS = 1, 2, 4, 8
+VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS, VEC_UNSUPPORTED = 1, 2, 4, 8, 16
 
 OK, ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, -1, -2, -3, -4, -5
 
@@ -43,6 +43,11 @@ class Desc(ctypes.Structure):
                 ("mod", ctypes.c_int32), ("mode", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("tau_mode", ctypes.c_int32), ("y_per_H", ctypes.c_int32),
                 ("t_max", ctypes.c_int32), ("flags", ctypes.c_int32), ("alpha", ctypes.c_float)]
+
+
+class MixedLaunch(ctypes.Structure):
+    """Persistent blocks per size bucket (N-1 <= 16, <= 32, <= 64); 0 = default."""
+    _fields_ = [("blocks", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -76,6 +81,11 @@ def load():
     lib.taser_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
     lib.taser_run.restype = ctypes.c_int
     lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.taser_mixed_workspace_size.restype = ctypes.c_int
+    lib.taser_mixed_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
+    lib.taser_run_mixed.restype = ctypes.c_int
+    lib.taser_run_mixed.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int32, _P,
+                                    ctypes.POINTER(MixedLaunch), _P, ctypes.c_size_t, _P]
     lib.taser_run_prep.restype = ctypes.c_int
     lib.taser_run_prep.argtypes = [D, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_solve.restype = ctypes.c_int
@@ -311,5 +321,52 @@ def run_solve(desc: Desc, out, want_margin=False, want_L=False, ws=None, device=
                              _need(res["status"], torch.int32, V, "status"),
                              _opt(res.get("L") if want_L else None, torch.float32, V * N * (N + 1) // 2, "L"),
                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream(dev))
+    _raise(st)
+    return res
+
+
+MIXED_STRIDE = 64
+
+
+def run_mixed(desc: Desc, Bv, Uv, modv, H_off, y_off, H, y, tau=None, want_margin=False,
+              blocks=None, out=None, ws=None):
+    """Mixed-size coherent batch in one call (``taser_run_mixed``).
+    Bv, Uv, modv: int32 [V]; H_off, y_off: int64 [V] (complex elements);
+    H, y: flat complex64 device tensors.  ``blocks``: persistent blocks per
+    bucket (3 ints, 0 = default), e.g. from the autotuner.  Returns dict with
+    sbar int8 [V, 64] (first N_v - 1 entries valid), status (+ margin)."""
+    torch = _torch()
+    lib = load()
+    V = desc.num_vectors
+    dev = y.device
+    for name, t, dt in (("B", Bv, torch.int32), ("U", Uv, torch.int32), ("mod", modv, torch.int32),
+                        ("H_off", H_off, torch.int64), ("y_off", y_off, torch.int64)):
+        _need(t, dt, V, name)
+    for name, t in (("H", H), ("y", y)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor")
+    pt = _need(tau, torch.float32, V, "tau") if desc.tau_mode == TAU_GIVEN else None
+    res = out if out is not None else {}
+    if "sbar" not in res:
+        res["sbar"] = torch.empty((V, MIXED_STRIDE), dtype=torch.int8, device=dev)
+        res["status"] = torch.empty((V,), dtype=torch.int32, device=dev)
+    if want_margin and "margin" not in res:
+        res["margin"] = torch.empty((V, MIXED_STRIDE), dtype=torch.float32, device=dev)
+    n = ctypes.c_size_t(0)
+    _raise(lib.taser_mixed_workspace_size(ctypes.byref(desc), ctypes.byref(n)))
+    if ws is None:
+        ws = _workspace(int(n.value), dev)
+    if ws.dtype != torch.uint8 or ws.numel() < n.value:
+        raise ValueError(f"workspace must be a uint8 CUDA tensor of at least {n.value} bytes")
+    launch = MixedLaunch()
+    if blocks is not None:
+        for i, b in enumerate(blocks):
+            launch.blocks[i] = int(b)
+    st = lib.taser_run_mixed(ctypes.byref(desc), *(ctypes.c_void_p(t.data_ptr()) for t in (Bv, Uv, modv, H_off, y_off, H, y)),
+                             pt, ctypes.c_void_p(res["sbar"].data_ptr()),
+                             ctypes.c_void_p(res["margin"].data_ptr()) if want_margin else None,
+                             ctypes.c_int32(MIXED_STRIDE), ctypes.c_void_p(res["status"].data_ptr()),
+                             ctypes.byref(launch), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                             _stream(dev))
     _raise(st)
     return res

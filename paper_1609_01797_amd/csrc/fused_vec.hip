@@ -152,11 +152,23 @@ struct VecLds {
   static constexpr int FLOATS = REGION + (N1 + 1) + N1;          // + D + shuffle buffer
 };
 
+// One vector's problem: where its inputs and outputs are and its sizes.
+struct VecJob {
+  long long v;            // vector index (status, tau_in)
+  int B, U, N, mod;
+  const float2* H;        // coherent: B x U row-major channel; JED: unused
+  const float2* y;        // coherent: y (B); JED: Y (U+1 slots x B)
+  float2 s0;              // JED pilot
+  int8_t* sbar;           // N-1 decisions
+  float* margin;          // N-1 margins or NULL
+  float* L;               // packed L~ or NULL
+  int pad_to;             // mixed batches: entries N-1 .. pad_to-1 of sbar/margin are set to 0
+};
+
 template <int NT, int P>
-__global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
+__device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, float* lds) {
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
-  __shared__ __align__(16) float lds[S::FLOATS];
   float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
   float2* stage = reinterpret_cast<float2*>(lds);  // aliases T while the Gram is accumulated
   float* Dl = lds + S::REGION;           // [N1+1]
@@ -165,10 +177,10 @@ __global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
   const int lane = threadIdx.x;
   const int n = lane & 15;
   const int g = lane >> 4;
-  const long long v = blockIdx.x;
-  const int B = a.B, U = a.U, Nm1 = a.N - 1;
+  const long long v = job.v;
+  const int B = job.B, U = job.U, Nm1 = job.N - 1;
   const bool jed = a.mode == TASER_JED;
-  const bool qpsk = a.mod == TASER_QPSK;
+  const bool qpsk = job.mod == TASER_QPSK;
   const float sg = jed ? -1.f : 1.f;
 
   // ---------------- preprocessing: complex Gram, H^H y, ||y||^2 ----------------
@@ -198,10 +210,9 @@ __global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < kEntriesPerLane; ++k) { are[k] = 0.f; aim[k] = 0.f; }
   const int W = U + 1;                         // stage row width (complex)
-  const float2* Hg = jed ? nullptr : a.H + (v / a.y_per_H) * (long long)B * U;
-  const float2* yg = jed ? a.y + v * (long long)(U + 1) * B : a.y + v * (long long)B;
-  float2 s0 = make_float2(1.f, 0.f);
-  if (jed) s0 = a.s0[v];
+  const float2* Hg = job.H;
+  const float2* yg = job.y;
+  const float2 s0 = job.s0;
   for (int b0 = 0; b0 < B; b0 += kChunk) {
     const int rows = min(kChunk, B - b0);
     for (int e = lane; e < rows * W; e += 64) {
@@ -553,6 +564,10 @@ __global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
   }
 
   // ---------------- slicing and outputs ----------------
+  for (int j = Nm1 + lane; j < job.pad_to; j += 64) {
+    job.sbar[j] = 0;
+    if (job.margin) job.margin[j] = 0.f;
+  }
   const int bits = skip ? (nonfinite ? TASER_VEC_NONFINITE : TASER_VEC_DEGENERATE) : st_bits;
   if (lane == 0) a.status[v] = bits;
   if (n == 0) {
@@ -563,15 +578,14 @@ __global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
         const int j = 16 * JT + 4 * r + g;
         if (j < Nm1) {
           const float x = skip ? 0.f : l21[JT][r];
-          a.sbar[v * Nm1 + j] = x >= 0.f ? (int8_t)1 : (int8_t)-1;
-          if (a.margin) a.margin[v * Nm1 + j] = skip ? 0.f : x / Dc[JT][r];
+          job.sbar[j] = x >= 0.f ? (int8_t)1 : (int8_t)-1;
+          if (job.margin) job.margin[j] = skip ? 0.f : x / Dc[JT][r];
         }
       }
     });
   }
-  if (a.L_out) {
-    const int Nn = Nm1 + 1;
-    float* Lo = a.L_out + v * (long long)(Nn * (Nn + 1) / 2);
+  if (job.L) {
+    float* Lo = job.L;
     sfor<0, NT>([&](auto ic) {
       constexpr int IT = decltype(ic)::value;
       sfor<0, IT + 1>([&](auto jc) {
@@ -601,6 +615,103 @@ __global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
   }
 }
 
+// One vector per block (uniform sizes).
+template <int NT, int P>
+__global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
+  __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
+  VecJob job;
+  job.v = blockIdx.x;
+  job.B = a.B; job.U = a.U; job.N = a.N; job.mod = a.mod;
+  const int Nm1 = a.N - 1;
+  if (a.mode == TASER_JED) {
+    job.H = nullptr;
+    job.y = a.y + job.v * (long long)(a.U + 1) * a.B;
+    job.s0 = a.s0[job.v];
+  } else {
+    job.H = a.H + (job.v / a.y_per_H) * (long long)a.B * a.U;
+    job.y = a.y + job.v * (long long)a.B;
+    job.s0 = make_float2(1.f, 0.f);
+  }
+  job.sbar = a.sbar + job.v * Nm1;
+  job.margin = a.margin ? a.margin + job.v * Nm1 : nullptr;
+  job.L = a.L_out ? a.L_out + job.v * (long long)(a.N * (a.N + 1) / 2) : nullptr;
+  job.pad_to = 0;
+  vec_body<NT, P>(a, job, lds);
+}
+
+// Mixed-size batch: a persistent grid walks the list of vectors of one size
+// bucket that the bucketing kernel left in the workspace.
+template <int NT, int P>
+__global__ __launch_bounds__(64) void fused_vec_mixed(FusedArgs a, MixedArgs m, int bucket) {
+  __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
+  const int count = m.count[bucket];
+  const int32_t* list = m.list + (long long)bucket * a.V;
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
+    VecJob job;
+    job.v = list[item];
+    job.B = m.Bv[job.v]; job.U = m.Uv[job.v]; job.mod = m.modv[job.v];
+    job.N = job.mod == TASER_QPSK ? 2 * job.U + 1 : job.U + 1;
+    job.H = a.H + m.H_off[job.v];
+    job.y = a.y + m.y_off[job.v];
+    job.s0 = make_float2(1.f, 0.f);
+    job.sbar = a.sbar + job.v * (long long)m.stride;
+    job.margin = a.margin ? a.margin + job.v * (long long)m.stride : nullptr;
+    job.L = nullptr;
+    job.pad_to = m.stride;
+    vec_body<NT, P>(a, job, lds);
+    __syncthreads();   // the next vector reuses the LDS
+  }
+}
+
+// Size bucket of a mixed-batch vector: 0 = N-1 <= 16, 1 = <= 32, 2 = <= 64,
+// -1 = beyond the fused kernels.
+__device__ __forceinline__ int mixed_bucket(int B, int U, int mod) {
+  if (B < 1 || U < 1 || U > 32 || (mod != TASER_BPSK && mod != TASER_QPSK)) return -1;
+  const int nm1 = mod == TASER_QPSK ? 2 * U : U;
+  return nm1 <= 16 ? 0 : (nm1 <= 32 ? 1 : (nm1 <= 64 ? 2 : -1));
+}
+
+__device__ __forceinline__ int modv_nm1(int U, int mod, int stride) {
+  const int nm1 = mod == TASER_QPSK ? 2 * U : U;
+  return nm1 < 0 ? 0 : (nm1 > stride ? stride : nm1);
+}
+
+__global__ void mixed_clear(int32_t* count) {
+  if (threadIdx.x < kMixedBuckets) count[threadIdx.x] = 0;
+}
+
+// Appends every vector to its bucket's list (order within a bucket is
+// arbitrary; each vector's result does not depend on it).  Vectors no fused
+// kernel covers get status TASER_VEC_UNSUPPORTED and decisions +1.
+__global__ void mixed_assign(FusedArgs a, MixedArgs m) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= a.V) return;
+  const int b = mixed_bucket(m.Bv[v], m.Uv[v], m.modv[v]);
+  if (b < 0) {
+    a.status[v] = TASER_VEC_UNSUPPORTED;
+    const int nm1 = modv_nm1(m.Uv[v], m.modv[v], m.stride);
+    for (int j = 0; j < m.stride; ++j) {
+      a.sbar[v * m.stride + j] = j < nm1 ? 1 : 0;
+      if (a.margin) a.margin[v * m.stride + j] = 0.f;
+    }
+    return;
+  }
+  const int slot = atomicAdd(&m.count[b], 1);
+  m.list[(long long)b * a.V + slot] = (int32_t)v;
+}
+
+template <int NT>
+bool launch_mixed_nt(const FusedArgs& a, const MixedArgs& m, int bucket, int blocks, hipStream_t s) {
+  const dim3 grid(blocks), block(64);
+  if (a.prec == TASER_PREC_BF16)
+    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_BF16>), grid, block, 0, s, a, m, bucket);
+  else if (a.prec == TASER_PREC_F16)
+    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
+  else
+    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+  return true;
+}
+
 template <int NT>
 bool launch_vec_nt(const FusedArgs& a, hipStream_t s) {
   const dim3 grid(a.V), block(64);
@@ -614,6 +725,28 @@ bool launch_vec_nt(const FusedArgs& a, hipStream_t s) {
 }
 
 }  // namespace
+
+size_t mixed_workspace_bytes(int V) {
+  return 256 + (size_t)kMixedBuckets * (size_t)V * sizeof(int32_t);
+}
+
+int mixed_default_blocks(int bucket) {
+  // persistent grid: blocks per launch for N-1 <= 16, <= 32, <= 64
+  static const int k[kMixedBuckets] = {8192, 4096, 1024};
+  return k[bucket];
+}
+
+hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s) {
+  hipLaunchKernelGGL(mixed_clear, dim3(1), dim3(64), 0, s, m.count);
+  hipLaunchKernelGGL(mixed_assign, dim3((a.V + 255) / 256), dim3(256), 0, s, a, m);
+  for (int b = 0; b < kMixedBuckets; ++b) {
+    const int g = blocks && blocks[b] > 0 ? blocks[b] : mixed_default_blocks(b);
+    if (b == 0) launch_mixed_nt<1>(a, m, b, g, s);
+    if (b == 1) launch_mixed_nt<2>(a, m, b, g, s);
+    if (b == 2) launch_mixed_nt<4>(a, m, b, g, s);
+  }
+  return hipGetLastError();
+}
 
 int fused_vec_tiles(const FusedArgs& a) {
   const int nm1 = a.N - 1;

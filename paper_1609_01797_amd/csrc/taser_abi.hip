@@ -199,4 +199,58 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
                                                                               : TASER_ERR_DEVICE;
 }
 
+static taser_status_t mixed_check(const taser_desc_t* d) {
+  if (!d) return TASER_ERR_ARG;
+  if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)
+    return TASER_ERR_ARG;
+  if (d->tau_mode != TASER_TAU_SPECTRAL && d->tau_mode != TASER_TAU_GIVEN) return TASER_ERR_ARG;
+  if (d->flags & ~TASER_FLAG_LITERAL_LAST) return TASER_ERR_ARG;
+  if (d->t_max < 0 || d->t_max > 100000) return TASER_ERR_ARG;
+  if (d->tau_mode == TASER_TAU_SPECTRAL && !(d->alpha > 0.f && d->alpha < 1.f)) return TASER_ERR_ARG;
+  if (d->mode != TASER_COHERENT) return TASER_ERR_UNSUPPORTED;
+  if (d->num_vectors < 0) return TASER_ERR_SHAPE;
+  return TASER_OK;
+}
+
+taser_status_t taser_mixed_workspace_size(const taser_desc_t* desc, size_t* bytes) {
+  if (!bytes) return TASER_ERR_ARG;
+  taser_status_t st = mixed_check(desc);
+  if (st != TASER_OK) return st;
+  *bytes = mixed_workspace_bytes(desc->num_vectors);
+  return TASER_OK;
+}
+
+taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, const int32_t* Uv,
+                               const int32_t* modv, const int64_t* H_off, const int64_t* y_off,
+                               const void* H, const void* y, const float* tau_in, int8_t* sbar,
+                               float* margin, int32_t stride, int32_t* status,
+                               const taser_mixed_launch_t* launch, void* ws, size_t ws_bytes,
+                               void* stream) {
+  taser_status_t st = mixed_check(desc);
+  if (st != TASER_OK) return st;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!Bv || !Uv || !modv || !H_off || !y_off || !H || !y || !sbar || !status) return TASER_ERR_ARG;
+  if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
+  if (stride < 64) return TASER_ERR_SHAPE;
+  if (launch)
+    for (int b = 0; b < kMixedBuckets; ++b)
+      if (launch->blocks[b] < 0 || launch->blocks[b] > (1 << 20)) return TASER_ERR_ARG;
+  const size_t need = mixed_workspace_bytes(desc->num_vectors);
+  if (!ws || ws_bytes < need) return TASER_ERR_WORKSPACE;
+  FusedArgs a{};
+  a.V = desc->num_vectors; a.mode = TASER_COHERENT; a.y_per_H = 1; a.t_max = desc->t_max;
+  a.flags = desc->flags; a.tau_mode = desc->tau_mode; a.prec = desc->prec; a.alpha = desc->alpha;
+  a.H = static_cast<const float2*>(H);
+  a.y = static_cast<const float2*>(y);
+  a.tau_in = tau_in; a.sbar = sbar; a.margin = margin; a.status = status;
+  MixedArgs m{};
+  m.Bv = Bv; m.Uv = Uv; m.modv = modv; m.H_off = H_off; m.y_off = y_off; m.stride = stride;
+  m.count = static_cast<int32_t*>(ws);
+  m.list = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
+  return launch_mixed(a, m, launch ? launch->blocks : nullptr, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
 }  // extern "C"

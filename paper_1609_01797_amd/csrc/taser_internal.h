@@ -54,6 +54,23 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s);
 
+// Mixed-size batches: per-vector sizes and offsets, and the bucket lists in
+// the workspace (count[kMixedBuckets] then kMixedBuckets lists of V indices).
+constexpr int kMixedBuckets = 3;
+struct MixedArgs {
+  const int32_t* Bv;
+  const int32_t* Uv;
+  const int32_t* modv;
+  const int64_t* H_off;   // complex elements
+  const int64_t* y_off;
+  int32_t stride;         // sbar / margin row stride
+  int32_t* count;
+  int32_t* list;
+};
+size_t mixed_workspace_bytes(int V);
+int mixed_default_blocks(int bucket);
+hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s);
+
 // LDS bytes the staged build kernel needs (0 if the shape does not fit).
 size_t build_T_lds_bytes(int B, int U, int N);
 size_t solve_lds_bytes(int N);

@@ -115,3 +115,23 @@ def test_binding_refuses_cpu_tensors():
     y = torch.zeros((2, 4), dtype=torch.complex64)
     with pytest.raises(ValueError):
         taser.build_T(d, H, y)
+
+
+def test_mixed_entry_rejects_bad_arguments():
+    lib = taser.load()
+    z = ctypes.c_void_p(0)
+    d = taser.make_desc(10, 1, 1, taser.QPSK, t_max=10)
+    n = ctypes.c_size_t(0)
+    assert lib.taser_mixed_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
+    assert n.value >= 3 * 10 * 4
+    jd = taser.make_desc(10, 1, 1, taser.QPSK, mode=taser.JED)
+    assert lib.taser_mixed_workspace_size(ctypes.byref(jd), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
+    launch = taser.MixedLaunch()
+    args = [z] * 7
+    assert lib.taser_run_mixed(ctypes.byref(d), *args, z, z, z, 64, z, ctypes.byref(launch), z, 0, z) == taser.ERR_ARG
+    one = ctypes.c_void_p(16)
+    ok_args = [one] * 7
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 32, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_SHAPE
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 8, z) == taser.ERR_WORKSPACE
+    launch.blocks[1] = -3
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
