@@ -56,9 +56,106 @@ def _time(fn, steps, warmup, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
+def run_mixed_workload(args):
+    """100,000 vectors, class uniform over {(64,8),(128,16),(256,32)} x
+    {BPSK, QPSK} (N from 9 to 65), own channel each, SNR 12 dB, t_max = 10,
+    in one taser_run_mixed call; default vs autotuned launch grids, eager vs
+    HIP-graph replay; FP32 / BF16 / FP16 products; paired BER vs the oracle
+    on a sample."""
+    import torch
+    import paper_1609_01797_amd as taser
+    from paper_1609_01797_amd import autotune
+    V, snr, t_max, alpha = 100000, 12.0, 10, 0.5
+    d = sim.gen_mixed(V, snr, sim.seed_for(3, snr_index=6))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    ins = (cu(d["B"]), cu(d["U"]), cu(d["mod"]), cu(d["H_off"]), cu(d["y_off"]), cu(d["H_flat"]), cu(d["y_flat"]))
+    nm1 = np.where(d["mod"] == 2, 2 * d["U"], d["U"])
+    truth = np.zeros((V, 64), dtype=np.int8)
+    for v in range(V):
+        s_ = d["s"][v]
+        row = np.concatenate([s_.real, s_.imag]) if d["mod"][v] == 2 else s_.real
+        truth[v, :nm1[v]] = row.astype(np.int8)
+    mask = np.arange(64)[None, :] < nm1[:, None]
+    # oracle on a sample of each class
+    import oracle
+    rng = np.random.default_rng(7)
+    t0 = time.perf_counter()
+    ref_err, ref_bits = 0, 0
+    samp = {}
+    for c in range(6):
+        idx = np.nonzero(d["cls"] == c)[0]
+        idx = np.sort(rng.choice(idx, size=min(400, len(idx)), replace=False))
+        Bc, Uc, mc = int(d["B"][idx[0]]), int(d["U"][idx[0]]), int(d["mod"][idx[0]])
+        H = np.stack([d["H_flat"][d["H_off"][v]:d["H_off"][v] + Bc * Uc].reshape(Bc, Uc) for v in idx])
+        y = np.stack([d["y_flat"][d["y_off"][v]:d["y_off"][v] + Bc] for v in idx])
+        sb = oracle.detect_coherent(H, y, mc, alpha=alpha, t_max=t_max)["sbar"]
+        samp[c] = (idx, sb)
+        ref_err += int(np.count_nonzero(sb != truth[idx, :sb.shape[1]]))
+        ref_bits += sb.size
+    cpu_s = time.perf_counter() - t0
+    n_samp = sum(len(v[0]) for v in samp.values())
+    paths = {}
+    flips = {}
+    for name, prec in (("bf16", 1), ("fp32", 0), ("fp16", 2)):
+        desc = taser.make_desc(V, 1, 1, 2, prec=prec, t_max=t_max, alpha=alpha)
+        ws = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
+        out = {}
+        call = lambda blocks=None: taser.run_mixed(desc, *ins, blocks=blocks, out=out, ws=ws)  # noqa: E731
+        ms_default = _time(lambda: call(None), args.steps, args.warmup, stream)
+        best, best_ms, _, trace = autotune.tune_mixed(desc, ins, reps=3)
+        ms_tuned = _time(lambda: call(best), args.steps, args.warmup, stream)
+        # graph replay of the tuned call
+        call(best)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            call(best)
+        ms_graph = _time(graph.replay, args.steps, args.warmup, stream)
+        sb = out["sbar"].cpu().numpy()
+        err = int(np.count_nonzero((sb != truth) & mask))
+        fl = 0
+        for c, (idx, rsb) in samp.items():
+            fl += int(np.count_nonzero(sb[idx, :rsb.shape[1]] != rsb))
+        flips[name] = fl
+        paths[name] = {"ms_default": ms_default, "ms_tuned": ms_tuned, "ms_graph": ms_graph,
+                       "tuned_blocks": best, "vectors_per_s": V / (min(ms_tuned, ms_graph) * 1e-3),
+                       "ber": err / int(mask.sum())}
+    # algorithmic flops per vector, averaged over the batch
+    fl_total = 0.0
+    for c in range(6):
+        idx = d["cls"] == c
+        Bc, Uc, mc = int(d["B"][idx][0]), int(d["U"][idx][0]), int(d["mod"][idx][0])
+        Nc = 2 * Uc + 1 if mc == 2 else Uc + 1
+        fl_total += idx.sum() * (loop_flops(Nc, t_max) + own_build_flops(Bc, Uc, Nc, mc))
+    fp32 = paths["fp32"]
+    ms = min(fp32["ms_tuned"], fp32["ms_graph"])
+    fp32["tflops"] = fl_total / (ms * 1e-3) / 1e12
+    fp32["frac_fp32_peak"] = fp32["tflops"] / PEAK_FP32
+    head = paths["bf16"]
+    return {"metric": "detected vectors/s @mixed (64,8)/(128,16)/(256,32) x BPSK/QPSK, one launch, t_max=10",
+            "value": head["vectors_per_s"], "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": min(head["ms_tuned"], head["ms_graph"]),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic",
+            "config": {"workload": "mixed", "vectors": V, "classes": [list(c) for c in sim.MIXED_CLASSES],
+                       "snr_db": snr, "t_max": t_max, "alpha": alpha, "tau": "spectral"},
+            "roofline_fp32": {"bound": "mfma", "achieved": fp32["tflops"], "peak": PEAK_FP32,
+                              "unit": "TFLOP/s", "frac": fp32["frac_fp32_peak"],
+                              "flops_per_vector_mean": fl_total / V},
+            "cpu_baseline": {"value": n_samp / cpu_s, "unit": "vectors/s", "cores": 1, "kind": "oracle",
+                             "sample": f"{n_samp} vectors (up to 400 per class), one process"},
+            "accuracy": {"ber_fp64_sample": ref_err / ref_bits, "paired_bit_flips_vs_fp64_sample": flips,
+                         "sample_bits": ref_bits},
+            "paths": paths}
+
+
 def run_workload(args):
     import torch
     import paper_1609_01797_amd as taser
+    if args.workload == "mixed":
+        return run_mixed_workload(args)
     if args.workload == "jed16x16":
         kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, 0.5
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0], 6.0, 16384
