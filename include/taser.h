@@ -207,6 +207,44 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* B, const
                                const taser_mixed_launch_t* launch, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* ---- Unfolded TASER (learned step sizes) --------------------------------
+
+   Algorithm 1 with one step size per iteration, tau_t = alpha_t / lam[v],
+   t = 0..t_max-1 (a constant alpha_t is the paper's algorithm), and the
+   gradient of a loss with respect to alpha.  Inputs per vector: T~ [V][N][N],
+   D [V][N] and lam [V] = ||T~||_2 (e.g. from taser_build_T).  real selects
+   float (TASER_REAL_F32, training) or double (TASER_REAL_F64, gradient
+   checks).  Every array has that element type.  N <= 64. */
+enum { TASER_REAL_F32 = 0, TASER_REAL_F64 = 1 };
+
+typedef struct {
+  int32_t num_vectors;  /* V */
+  int32_t N;            /* problem size, 2..64 */
+  int32_t t_max;        /* iterations, 1..10000 */
+  int32_t real;         /* TASER_REAL_* */
+  int32_t ckpt_every;   /* c >= 1: L is stored before iterations 0, c, 2c, ... */
+  int32_t flags;        /* TASER_FLAG_LITERAL_LAST or 0 */
+} taser_unfolded_t;
+
+/* Elements (not bytes) of the checkpoint buffer: V * ceil(t_max/c) * N(N+1)/2;
+   bytes of the backward workspace: V * t_max * sizeof(real). */
+taser_status_t taser_unfolded_sizes(const taser_unfolded_t* u, size_t* ckpt_elems,
+                                    size_t* ws_bytes);
+
+/* Forward: L_out [V][N(N+1)/2] (packed rows) after t_max iterations; the
+   checkpoints L_ckpt (layout [V][ceil(t_max/c)][N(N+1)/2]) for the backward. */
+taser_status_t taser_unfolded_forward(const taser_unfolded_t* u, const void* Tt, const void* D,
+                                      const void* lam, const void* alpha_t, void* L_ckpt,
+                                      void* L_out, void* stream);
+
+/* Backward: given dL [V][N(N+1)/2] = dLoss/dL_out, writes
+   dalpha [t_max] = dLoss/dalpha_t summed over the batch (deterministic:
+   fixed-order reduction over vectors).  ws: taser_unfolded_sizes() bytes. */
+taser_status_t taser_unfolded_backward(const taser_unfolded_t* u, const void* Tt, const void* D,
+                                       const void* lam, const void* alpha_t, const void* L_ckpt,
+                                       const void* dL, void* dalpha, void* ws, size_t ws_bytes,
+                                       void* stream);
+
 #ifdef __cplusplus
 }
 #endif

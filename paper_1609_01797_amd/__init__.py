@@ -17,7 +17,8 @@ import os
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
            "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
-           "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH"]
+           "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
+           "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
 
 LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                       "libtaser.so")
@@ -49,6 +50,13 @@ class MixedLaunch(ctypes.Structure):
     """Persistent blocks per size bucket (N-1 <= 16, <= 32, <= 64); 0 = default."""
     _fields_ = [("blocks", ctypes.c_int32 * 3)]
 
+
+class UnfoldedDesc(ctypes.Structure):
+    _fields_ = [("num_vectors", ctypes.c_int32), ("N", ctypes.c_int32), ("t_max", ctypes.c_int32),
+                ("real", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+REAL_F32, REAL_F64 = 0, 1
 
 _lib = None
 _P = ctypes.c_void_p
@@ -90,6 +98,14 @@ def load():
     lib.taser_run_prep.argtypes = [D, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_solve.restype = ctypes.c_int
     lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    U = ctypes.POINTER(UnfoldedDesc)
+    lib.taser_unfolded_sizes.restype = ctypes.c_int
+    lib.taser_unfolded_sizes.argtypes = [U, ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.POINTER(ctypes.c_size_t)]
+    lib.taser_unfolded_forward.restype = ctypes.c_int
+    lib.taser_unfolded_forward.argtypes = [U, _P, _P, _P, _P, _P, _P, _P]
+    lib.taser_unfolded_backward.restype = ctypes.c_int
+    lib.taser_unfolded_backward.argtypes = [U, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     _lib = lib
     return lib
 
@@ -370,3 +386,73 @@ def run_mixed(desc: Desc, Bv, Uv, modv, H_off, y_off, H, y, tau=None, want_margi
                              _stream(dev))
     _raise(st)
     return res
+
+
+# ---- Unfolded TASER (per-iteration step sizes) ----------------------------
+
+def _unf_desc(Tt, alpha, ckpt_every, literal_last):
+    torch = _torch()
+    if Tt.dim() != 3 or Tt.shape[1] != Tt.shape[2]:
+        raise ValueError("Tt must be [V, N, N]")
+    if Tt.dtype not in (torch.float32, torch.float64):
+        raise ValueError("Tt must be float32 or float64")
+    V, N = Tt.shape[0], Tt.shape[1]
+    t_max = alpha.numel()
+    real = REAL_F64 if Tt.dtype == torch.float64 else REAL_F32
+    flags = FLAG_LITERAL_LAST if literal_last else 0
+    if ckpt_every:
+        return UnfoldedDesc(V, N, t_max, real, int(ckpt_every), flags)
+    # default: about sqrt(t_max) states per segment, fewer if the segment
+    # would not fit in the 160 KiB of LDS
+    c = max(1, int(round(t_max ** 0.5)))
+    while c > 1 and load().taser_unfolded_sizes(
+            ctypes.byref(UnfoldedDesc(V, N, t_max, real, c, flags)),
+            ctypes.byref(ctypes.c_size_t()), ctypes.byref(ctypes.c_size_t())) == ERR_UNSUPPORTED:
+        c -= 1
+    return UnfoldedDesc(V, N, t_max, real, c, flags)
+
+
+def unfolded_sizes(u: UnfoldedDesc):
+    """(checkpoint elements, backward workspace bytes) for ``u``."""
+    ck, ws = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _raise(load().taser_unfolded_sizes(ctypes.byref(u), ctypes.byref(ck), ctypes.byref(ws)))
+    return int(ck.value), int(ws.value)
+
+
+def unfolded_forward(Tt, D, lam, alpha, ckpt_every=None, literal_last=False):
+    """Algorithm 1 with tau_t = alpha[t] / lam.  Tt [V,N,N], D [V,N], lam [V],
+    alpha [t_max], all float32 or all float64 on one device.  Returns
+    (L packed [V, N(N+1)/2], checkpoints, desc) for ``unfolded_backward``."""
+    torch = _torch()
+    lib = load()
+    u = _unf_desc(Tt, alpha, ckpt_every, literal_last)
+    V, N, dt = u.num_vectors, u.N, Tt.dtype
+    n_ck, _ = unfolded_sizes(u)
+    ckpt = torch.empty((max(n_ck, 1),), dtype=dt, device=Tt.device)
+    L = torch.empty((V, N * (N + 1) // 2), dtype=dt, device=Tt.device)
+    st = lib.taser_unfolded_forward(ctypes.byref(u), _need(Tt, dt, V * N * N, "Tt"),
+                                    _need(D, dt, V * N, "D"), _need(lam, dt, V, "lam"),
+                                    _need(alpha, dt, u.t_max, "alpha"),
+                                    ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(L.data_ptr()),
+                                    _stream(Tt.device))
+    _raise(st)
+    return L, ckpt, u
+
+
+def unfolded_backward(u: UnfoldedDesc, Tt, D, lam, alpha, ckpt, dL):
+    """dLoss/dalpha [t_max] (summed over the batch) given dL = dLoss/dL_out."""
+    torch = _torch()
+    lib = load()
+    V, N, dt = u.num_vectors, u.N, Tt.dtype
+    _, ws_bytes = unfolded_sizes(u)
+    ws = torch.empty((max(ws_bytes, 8),), dtype=torch.uint8, device=Tt.device)
+    dalpha = torch.empty((u.t_max,), dtype=dt, device=Tt.device)
+    st = lib.taser_unfolded_backward(ctypes.byref(u), _need(Tt, dt, V * N * N, "Tt"),
+                                     _need(D, dt, V * N, "D"), _need(lam, dt, V, "lam"),
+                                     _need(alpha, dt, u.t_max, "alpha"),
+                                     ctypes.c_void_p(ckpt.data_ptr()),
+                                     _need(dL, dt, V * N * (N + 1) // 2, "dL"),
+                                     ctypes.c_void_p(dalpha.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(Tt.device))
+    _raise(st)
+    return dalpha

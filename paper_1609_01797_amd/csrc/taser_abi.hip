@@ -253,4 +253,59 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, cons
              : TASER_ERR_DEVICE;
 }
 
+static taser_status_t unf_check(const taser_unfolded_t* u) {
+  if (!u) return TASER_ERR_ARG;
+  if (u->real != TASER_REAL_F32 && u->real != TASER_REAL_F64) return TASER_ERR_ARG;
+  if (u->flags & ~TASER_FLAG_LITERAL_LAST) return TASER_ERR_ARG;
+  if (u->num_vectors < 0 || u->N < 2 || u->N > 64) return TASER_ERR_SHAPE;
+  if (u->t_max < 1 || u->t_max > 10000 || u->ckpt_every < 1) return TASER_ERR_SHAPE;
+  UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
+  if (unfolded_lds_bytes(a) > 163840) return TASER_ERR_UNSUPPORTED;
+  return TASER_OK;
+}
+
+taser_status_t taser_unfolded_sizes(const taser_unfolded_t* u, size_t* ckpt_elems,
+                                    size_t* ws_bytes) {
+  taser_status_t st = unf_check(u);
+  if (st != TASER_OK) return st;
+  if (!ckpt_elems || !ws_bytes) return TASER_ERR_ARG;
+  const size_t P = (size_t)u->N * (u->N + 1) / 2;
+  const size_t nck = (size_t)(u->t_max + u->ckpt_every - 1) / u->ckpt_every;
+  *ckpt_elems = (size_t)u->num_vectors * nck * P;
+  UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
+  *ws_bytes = unfolded_workspace_bytes(a);
+  return TASER_OK;
+}
+
+taser_status_t taser_unfolded_forward(const taser_unfolded_t* u, const void* Tt, const void* D,
+                                      const void* lam, const void* alpha_t, void* L_ckpt,
+                                      void* L_out, void* stream) {
+  taser_status_t st = unf_check(u);
+  if (st != TASER_OK) return st;
+  if (u->num_vectors == 0) return TASER_OK;
+  if (!Tt || !D || !lam || !alpha_t || !L_ckpt || !L_out) return TASER_ERR_ARG;
+  UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
+  return launch_unfolded_forward(a, Tt, D, lam, alpha_t, L_ckpt, L_out,
+                                 static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
+taser_status_t taser_unfolded_backward(const taser_unfolded_t* u, const void* Tt, const void* D,
+                                       const void* lam, const void* alpha_t, const void* L_ckpt,
+                                       const void* dL, void* dalpha, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  taser_status_t st = unf_check(u);
+  if (st != TASER_OK) return st;
+  if (!Tt || !D || !lam || !alpha_t || !L_ckpt || !dL || !dalpha) return TASER_ERR_ARG;
+  UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
+  const size_t need = unfolded_workspace_bytes(a);
+  if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
+  if (u->num_vectors == 0) return TASER_OK;
+  return launch_unfolded_backward(a, Tt, D, lam, alpha_t, L_ckpt, dL, dalpha, ws,
+                                  static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
 }  // extern "C"

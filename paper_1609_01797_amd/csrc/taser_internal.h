@@ -71,6 +71,19 @@ size_t mixed_workspace_bytes(int V);
 int mixed_default_blocks(int bucket);
 hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s);
 
+// Unfolded variant (per-iteration step sizes) and its adjoint.
+struct UnfoldedArgs {
+  int32_t V, N, t_max, real, ckpt_every, flags;
+};
+size_t unfolded_lds_bytes(const UnfoldedArgs& a);
+size_t unfolded_workspace_bytes(const UnfoldedArgs& a);
+hipError_t launch_unfolded_forward(const UnfoldedArgs& a, const void* Tt, const void* D,
+                                   const void* lam, const void* alpha, void* ckpt, void* Lout,
+                                   hipStream_t s);
+hipError_t launch_unfolded_backward(const UnfoldedArgs& a, const void* Tt, const void* D,
+                                    const void* lam, const void* alpha, const void* ckpt,
+                                    const void* dL, void* dalpha, void* ws, hipStream_t s);
+
 // LDS bytes the staged build kernel needs (0 if the shape does not fit).
 size_t build_T_lds_bytes(int B, int U, int N);
 size_t solve_lds_bytes(int N);

@@ -135,3 +135,37 @@ def test_mixed_entry_rejects_bad_arguments():
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 8, z) == taser.ERR_WORKSPACE
     launch.blocks[1] = -3
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
+
+
+def test_unfolded_sizes_and_rejects():
+    """Shape and argument checks of the unfolded entry points run on the
+    host before any device call."""
+    lib = taser.load()
+    U = taser.UnfoldedDesc
+    ck, ws = ctypes.c_size_t(0), ctypes.c_size_t(0)
+
+    def sizes(u):
+        return lib.taser_unfolded_sizes(ctypes.byref(u), ctypes.byref(ck), ctypes.byref(ws))
+
+    assert sizes(U(10, 33, 20, taser.REAL_F32, 5, 0)) == taser.OK
+    assert (ck.value, ws.value) == (10 * 4 * 561, 10 * 20 * 4)
+    assert sizes(U(3, 9, 5, taser.REAL_F64, 2, taser.FLAG_LITERAL_LAST)) == taser.OK
+    assert (ck.value, ws.value) == (3 * 3 * 45, 3 * 5 * 8)
+    assert sizes(U(1, 65, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
+    assert sizes(U(1, 1, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
+    assert sizes(U(1, 9, 0, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
+    assert sizes(U(1, 9, 5, taser.REAL_F32, 0, 0)) == taser.ERR_SHAPE
+    assert sizes(U(-1, 9, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
+    assert sizes(U(1, 9, 5, 2, 1, 0)) == taser.ERR_ARG
+    assert sizes(U(1, 9, 5, taser.REAL_F32, 1, 4)) == taser.ERR_ARG
+    # a segment of 64 FP64 states does not fit in LDS
+    assert sizes(U(1, 64, 64, taser.REAL_F64, 64, 0)) == taser.ERR_UNSUPPORTED
+    z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)
+    u = U(4, 9, 5, taser.REAL_F32, 2, 0)
+    assert lib.taser_unfolded_forward(ctypes.byref(u), one, one, one, one, z, one, z) == taser.ERR_ARG
+    assert lib.taser_unfolded_backward(ctypes.byref(u), one, one, one, one, one, one, one, one, 8,
+                                       z) == taser.ERR_WORKSPACE
+    assert lib.taser_unfolded_backward(ctypes.byref(u), one, one, one, one, one, z, one, one, 1 << 20,
+                                       z) == taser.ERR_ARG
+    empty = U(0, 9, 5, taser.REAL_F32, 2, 0)
+    assert lib.taser_unfolded_forward(ctypes.byref(empty), z, z, z, z, z, z, z) == taser.OK
