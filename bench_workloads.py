@@ -151,11 +151,147 @@ def run_mixed_workload(args):
             "paths": paths}
 
 
+def run_unfolded_workload(args):
+    """Unfolded TASER with learned step sizes, B = 64, U = 16 QPSK (N = 33):
+    training steps/s at batch 16,384 (fresh channels, symbols and noise per
+    step, SNR uniform in [4, 16] dB; preprocessing by the staged kernel,
+    forward and adjoint by the unfolded kernels, Adam on alpha), then BER
+    vs depth on held-out data: schedules learned at depths 5, 10 and 20
+    against plain TASER (constant alpha) at t_max = 20 and 10."""
+    import torch
+    import paper_1609_01797_amd as taser
+    import paper_1609_01797_amd.unfolded as unf
+    B, U, mod, batch, t_train = 64, 16, 2, 16384, 20
+    N = 2 * U + 1
+    alpha0 = float(getattr(args, "alpha", None) or 0.5)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    def prep(d):
+        V = d["y"].shape[0]
+        desc = taser.make_desc(V, B, U, mod, t_max=1, alpha=0.5)
+        r = taser.build_T(desc, d["H"].contiguous(), d["y"].contiguous())
+        s_ = d["s"]
+        sbar = torch.cat([s_.real, s_.imag], dim=1)
+        return r["Tt"], r["D"], r["lam"], sbar
+
+    def train(depth, steps, seed0):
+        alpha = torch.full((depth,), alpha0, dtype=torch.float32, device=dev, requires_grad=True)
+        opt = torch.optim.Adam([alpha], lr=0.02)
+        for i in range(steps):
+            Tt, D, lam, sbar = prep(sim.gen_training_batch_torch(B, U, mod, batch, 4.0, 16.0,
+                                                                 seed0 + i, dev))
+            opt.zero_grad()
+            loss = unf.mse_loss(unf.unfolded(alpha, Tt, D, lam), D, sbar)
+            loss.backward()
+            opt.step()
+        return alpha.detach()
+
+    # training steps/s (depth 20): generation + preprocessing + forward +
+    # adjoint + Adam, timed with HIP events around each step
+    alpha = torch.full((t_train,), alpha0, dtype=torch.float32, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([alpha], lr=0.02)
+    k_fwd, k_bwd = [], []
+
+    def step(i, timed=False):
+        Tt, D, lam, sbar = prep(sim.gen_training_batch_torch(B, U, mod, batch, 4.0, 16.0,
+                                                             sim.seed_for(4, 0, i), dev))
+        opt.zero_grad()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        L = unf.unfolded(alpha, Tt, D, lam)
+        e[1].record(stream)
+        loss = unf.mse_loss(L, D, sbar)
+        loss.backward()
+        e[2].record(stream)
+        opt.step()
+        if timed:
+            k_fwd.append(e)
+    ms_step = _time(lambda: step(0), args.steps, args.warmup, stream)
+    for i in range(5):
+        step(i, timed=True)
+    torch.cuda.synchronize()
+    ms_fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in k_fwd]))
+    ms_fwd_bwd = float(np.mean([e[0].elapsed_time(e[2]) for e in k_fwd]))
+
+    # learned schedules at depths 5, 10, 20
+    train_steps = int(os.environ.get("TASER_UNFOLDED_TRAIN_STEPS", "150"))
+    t0 = time.perf_counter()
+    learned = {d: train(d, train_steps, sim.seed_for(4, 1, 0) + 1000 * d) for d in (5, 10, 20)}
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    # held-out BER, 65,536 vectors per SNR point
+    snrs = list(range(4, 17, 2))
+    ber = {f"plain_t{t}": [] for t in (10, 20)}
+    ber.update({f"learned_t{d}": [] for d in learned})
+    for si, snr in enumerate(snrs):
+        d = sim.gen_training_batch_torch(B, U, mod, 65536, float(snr), float(snr),
+                                         sim.seed_for(4, 2 + si, 0), dev)
+        Tt, D, lam, sbar = prep(d)
+        truth = sbar.to(torch.int8)
+        for t in (10, 20):
+            desc = taser.make_desc(65536, B, U, mod, t_max=t, alpha=alpha0)
+            r = taser.run(desc, d["H"].contiguous(), d["y"].contiguous())
+            ber[f"plain_t{t}"].append(float((r["sbar"] != truth).float().mean()))
+        for dep, a in learned.items():
+            with torch.no_grad():
+                L = unf.unfolded(a, Tt, D, lam)
+            dec = torch.where(unf.last_row(L, N) >= 0, 1, -1).to(torch.int8)
+            ber[f"learned_t{dep}"].append(float((dec != truth).float().mean()))
+
+    def smallest_depth(ref):
+        for dep in sorted(learned):
+            if all(b <= r for b, r in zip(ber[f"learned_t{dep}"], ber[ref])):
+                return dep
+        return None
+
+    # oracle baseline: FP64 torch autograd of the same forward, bounded sample
+    import oracle.unfolded as ounf
+    dd = sim.gen_training_batch(B, U, mod, 256, 4.0, 16.0, sim.seed_for(4, 9, 0))
+    import oracle
+    T = oracle.build_T_coherent(dd["H"], dd["y"], mod)
+    Dn, Ttn, _ = oracle.precondition(T)
+    lamn = oracle.spectral_norm(Ttn)
+    sb = np.concatenate([dd["s"].real, dd["s"].imag], axis=1)
+    Tt_, D_, lam_, sb_ = (torch.from_numpy(np.asarray(x, dtype=np.float64)) for x in (Ttn, Dn, lamn, sb))
+    a = torch.full((t_train,), alpha0, dtype=torch.float64, requires_grad=True)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 10.0:
+        ounf.last_row_mse(ounf.unfolded_forward(Tt_, D_, lam_, a), D_, sb_).backward()
+        reps += 1
+    cpu_s = (time.perf_counter() - t0) / reps
+    cpu_steps_per_s = 256 / batch / cpu_s
+    flops_fwd = loop_flops(N, t_train)
+    return {"metric": "unfolded TASER training steps/s @64x16 QPSK, t_max=20, batch 16384",
+            "value": 1e3 / ms_step, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "unfolded64x16", "B": B, "U": U, "modulation": "QPSK", "N": N,
+                       "batch": batch, "t_max": t_train, "snr_train_db": [4, 16],
+                       "alpha_init": alpha0, "optimizer": "Adam lr 0.02",
+                       "train_steps_per_depth": train_steps},
+            "kernels": {"ms_forward": ms_fwd, "ms_forward_backward": ms_fwd_bwd,
+                        "forward_tflops": batch * flops_fwd / (ms_fwd * 1e-3) / 1e12},
+            "cpu_baseline": {"value": cpu_steps_per_s, "unit": "steps/s", "cores": torch.get_num_threads(),
+                             "kind": "oracle",
+                             "sample": "FP64 torch autograd of the unfolded forward on 256 vectors, "
+                                       "scaled to a 16,384 batch"},
+            "ber_vs_depth": {"snr_db": snrs, "vectors_per_snr": 65536, "ber": ber,
+                             "learned_alpha": {d: a.cpu().tolist() for d, a in learned.items()},
+                             "train_seconds": train_s,
+                             "smallest_depth_matching_plain_t20": smallest_depth("plain_t20"),
+                             "smallest_depth_matching_plain_t10": smallest_depth("plain_t10")}}
+
+
 def run_workload(args):
     import torch
     import paper_1609_01797_amd as taser
     if args.workload == "mixed":
         return run_mixed_workload(args)
+    if args.workload == "unfolded64x16":
+        return run_unfolded_workload(args)
     if args.workload == "jed16x16":
         kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, 0.5
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0], 6.0, 16384

@@ -76,6 +76,18 @@ struct UnfoldedArgs {
   int32_t V, N, t_max, real, ckpt_every, flags;
 };
 size_t unfolded_lds_bytes(const UnfoldedArgs& a);
+// LDS bytes of `states` N x N states with rows padded to a multiple of 4.
+inline size_t unfolded_lds_states(int N, int states, size_t elem) {
+  const size_t NS = (size_t)((N + 3) & ~3);
+  return (size_t)states * NS * NS * elem;
+}
+// Per register bucket NP (multiple of 8, >= N); instantiated for float and double.
+template <int NP, typename Real>
+hipError_t unf_fwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
+                   const void* alpha, void* ckpt, void* Lout, hipStream_t s);
+template <int NP, typename Real>
+hipError_t unf_bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
+                   const void* alpha, const void* ckpt, const void* dL, void* ws, hipStream_t s);
 size_t unfolded_workspace_bytes(const UnfoldedArgs& a);
 hipError_t launch_unfolded_forward(const UnfoldedArgs& a, const void* Tt, const void* D,
                                    const void* lam, const void* alpha, void* ckpt, void* Lout,

@@ -1,0 +1,17 @@
+// Unfolded TASER kernels in double, register buckets 40, 48.
+#include "unfolded_kernels.h"
+
+namespace taser {
+
+template hipError_t unf_fwd<40, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<40, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+template hipError_t unf_fwd<48, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<48, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+
+}  // namespace taser

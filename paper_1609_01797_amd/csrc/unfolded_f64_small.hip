@@ -1,0 +1,27 @@
+// Unfolded TASER kernels in double, register buckets 8, 16, 24, 32.
+#include "unfolded_kernels.h"
+
+namespace taser {
+
+template hipError_t unf_fwd<8, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<8, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+template hipError_t unf_fwd<16, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<16, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+template hipError_t unf_fwd<24, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<24, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+template hipError_t unf_fwd<32, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<32, double>(const UnfoldedArgs&, const void*, const void*,
+                                        const void*, const void*, const void*, const void*,
+                                        void*, hipStream_t);
+
+}  // namespace taser

@@ -178,3 +178,34 @@ def gen_training_batch(B: int, U: int, mod: int, batch: int, snr_lo: float,
     y = np.einsum("vbu,vu->vb", H, s) + n
     return {"H": H.astype(np.complex64), "s": s.astype(np.complex64),
             "y": y.astype(np.complex64), "snr_db": snr}
+
+
+def gen_training_batch_torch(B: int, U: int, mod: int, batch: int, snr_lo: float,
+                             snr_hi: float, seed: int, device) -> dict:
+    """``gen_training_batch`` drawn on ``device`` with torch's generator (same
+    distributions, not the same numbers): fresh training data for long
+    training runs without host-side generation.  Returns complex64 tensors
+    H [batch, B, U], s [batch, U], y [batch, B] and snr_db [batch]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+
+    def cn(shape, var):
+        sd = torch.sqrt(torch.as_tensor(var, dtype=torch.float32, device=device) / 2.0)
+        re = torch.randn(shape, generator=g, device=device)
+        im = torch.randn(shape, generator=g, device=device)
+        if sd.dim():
+            sd = sd.reshape(sd.shape + (1,) * (len(shape) - sd.dim()))
+        return torch.complex(re * sd, im * sd)
+
+    def bits(shape):
+        return (torch.randint(0, 2, shape, generator=g, device=device) * 2 - 1).float()
+
+    H = cn((batch, B, U), 1.0)
+    re = bits((batch, U))
+    im = bits((batch, U)) if mod == QPSK else torch.zeros_like(re)
+    s = torch.complex(re, im)
+    snr = snr_lo + (snr_hi - snr_lo) * torch.rand(batch, generator=g, device=device)
+    N0 = U * symbol_energy(mod) * 10.0 ** (-snr / 10.0)
+    y = (H * s[:, None, :]).sum(-1) + cn((batch, B), N0)
+    return {"H": H, "s": s, "y": y, "snr_db": snr}
