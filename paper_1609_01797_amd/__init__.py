@@ -402,13 +402,12 @@ def _unf_desc(Tt, alpha, ckpt_every, literal_last):
     flags = FLAG_LITERAL_LAST if literal_last else 0
     if ckpt_every:
         return UnfoldedDesc(V, N, t_max, real, int(ckpt_every), flags)
-    # default: about sqrt(t_max) states per segment, fewer if the segment
-    # would not fit in the 160 KiB of LDS
-    c = max(1, int(round(t_max ** 0.5)))
-    while c > 1 and load().taser_unfolded_sizes(
-            ctypes.byref(UnfoldedDesc(V, N, t_max, real, c, flags)),
-            ctypes.byref(ctypes.c_size_t()), ctypes.byref(ctypes.c_size_t())) == ERR_UNSUPPORTED:
-        c -= 1
+    # default: a checkpoint every 2 iterations.  The backward keeps c + 1
+    # states in LDS; on gfx950 c = 2 gave the fastest backward (1.5x faster
+    # than c = 4 ~ sqrt(20), whose LDS footprint halves the waves per CU;
+    # c = 1 waits on a checkpoint load from HBM every step), and the
+    # checkpoints cost V * t_max/2 * N(N+1)/2 values of HBM.
+    c = min(2, t_max)
     return UnfoldedDesc(V, N, t_max, real, c, flags)
 
 

@@ -21,9 +21,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled on purpose: the compiler must not
-# form v_pk_* float ops from ordinary float code.
+# form v_pk_* float ops from ordinary float code.  MFMA accumulators are
+# kept in ordinary VGPRs (gfx950 has one unified register file): with
+# AGPR accumulators every MFMA result needs a v_accvgpr_read before the
+# vector ALUs can use it, one extra instruction per output value in the
+# prox-bound solve loops.
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 
 

@@ -685,19 +685,34 @@ __global__ void mixed_clear(int32_t* count) {
 // kernel covers get status TASER_VEC_UNSUPPORTED and decisions +1.
 __global__ void mixed_assign(FusedArgs a, MixedArgs m) {
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (v >= a.V) return;
-  const int b = mixed_bucket(m.Bv[v], m.Uv[v], m.modv[v]);
-  if (b < 0) {
-    a.status[v] = TASER_VEC_UNSUPPORTED;
-    const int nm1 = modv_nm1(m.Uv[v], m.modv[v], m.stride);
-    for (int j = 0; j < m.stride; ++j) {
-      a.sbar[v * m.stride + j] = j < nm1 ? 1 : 0;
-      if (a.margin) a.margin[v * m.stride + j] = 0.f;
+  int b = -2;                                   // -2: past the end, -1: unsupported size
+  if (v < a.V) {
+    b = mixed_bucket(m.Bv[v], m.Uv[v], m.modv[v]);
+    if (b < 0) {
+      a.status[v] = TASER_VEC_UNSUPPORTED;
+      const int nm1 = modv_nm1(m.Uv[v], m.modv[v], m.stride);
+      for (int j = 0; j < m.stride; ++j) {
+        a.sbar[v * m.stride + j] = j < nm1 ? 1 : 0;
+        if (a.margin) a.margin[v * m.stride + j] = 0.f;
+      }
     }
-    return;
   }
-  const int slot = atomicAdd(&m.count[b], 1);
-  m.list[(long long)b * a.V + slot] = (int32_t)v;
+  // One atomic per wave and bucket: the lanes of a bucket take consecutive
+  // slots after the wave's base (a per-lane atomic on three counters
+  // serialises 10^5 updates).
+  const int lane = threadIdx.x & 63;
+  for (int bk = 0; bk < kMixedBuckets; ++bk) {
+    const unsigned long long mask = __ballot(b == bk);
+    if (mask == 0ull) continue;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&m.count[bk], (int)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (b == bk) {
+      const int rank = (int)__popcll(mask & ((1ull << lane) - 1ull));
+      m.list[(long long)bk * a.V + base + rank] = (int32_t)v;
+    }
+  }
 }
 
 template <int NT>

@@ -76,9 +76,9 @@ struct UnfoldedArgs {
   int32_t V, N, t_max, real, ckpt_every, flags;
 };
 size_t unfolded_lds_bytes(const UnfoldedArgs& a);
-// LDS bytes of `states` N x N states with rows padded to a multiple of 4.
+// LDS bytes of `states` N x N states stored NP x NP, NP = N rounded up to 8.
 inline size_t unfolded_lds_states(int N, int states, size_t elem) {
-  const size_t NS = (size_t)((N + 3) & ~3);
+  const size_t NS = (size_t)((N + 7) & ~7);
   return (size_t)states * NS * NS * elem;
 }
 // Per register bucket NP (multiple of 8, >= N); instantiated for float and double.
