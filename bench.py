@@ -3,8 +3,9 @@
 
 Workload: coherent MU-MIMO uplink, B = 128 receive antennas, U = 16 QPSK
 users (real problem size N = 33), 4,096 independent Rayleigh channels each
-shared by 16 received vectors (65,536 vectors), t_max = 10, alpha = 0.5,
-tau = alpha/||T~||_2 computed on the GPU.  One step is the whole detector
+shared by 16 received vectors (65,536 vectors), t_max = 10, alpha from the
+oracle's sweep (tests/golden/alpha_star.json), tau = alpha/||T~||_2 computed
+on the GPU.  One step is the whole detector
 over the batch with inputs resident in HBM: the preparation kernel (T,
 Jacobi preconditioning, step size) and the solve kernel (t_max iterations,
 slicing).  The headline value is the BF16-product path; the FP32 and FP16
@@ -35,13 +36,14 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import sim  # noqa: E402
+from bench_workloads import alpha_star  # noqa: E402
 
 METRIC = "detected vectors/s @128×16 QPSK t_max=10 (BF16/batched vs FP32), BER gap vs FP64"
 B, U, MOD, N = 128, 16, 2, 33
 NUM_H, Y_PER_H = 4096, 16
 V = NUM_H * Y_PER_H
 T_MAX = 10
-ALPHA = 0.5
+ALPHA = alpha_star("coherent128x16")   # oracle sweep, tests/golden/alpha_star.json
 SNR_TIMED = 10.0
 SNR_SWEEP = [-4.0, -2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0, 14.0, 16.0, 18.0, 20.0]
 SNR_ORACLE = [-4.0, -2.0, 0.0, 2.0, 4.0, 10.0]      # errors vanish above 4 dB at this size
@@ -252,6 +254,28 @@ def main():
         timing[name] = {"ms_per_step": ms_step, "vectors_per_s": V / (ms_step * 1e-3),
                         "prep_kernel_ms": prep_ms, "solve_kernel_ms": solve_ms,
                         "status_nonzero": int(torch.count_nonzero(out["status"]).item())}
+        # the same step captured once in a HIP graph: 20 warm-up replays, then
+        # 200 replays timed one by one (median, p10, p90)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            taser.run_prep(desc, H, y, out=out, ws=ws)
+            taser.run_solve(desc, out, ws=ws)
+        for _ in range(20):
+            graph.replay()
+        torch.cuda.synchronize()
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(200)]
+        for e0, e1 in gev:
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        g_ms = np.array([e0.elapsed_time(e1) for e0, e1 in gev])
+        timing[name]["graph_replay"] = {"median_ms": float(np.median(g_ms)),
+                                        "p10_ms": float(np.percentile(g_ms, 10)),
+                                        "p90_ms": float(np.percentile(g_ms, 90)),
+                                        "vectors_per_s_median": V / (float(np.median(g_ms)) * 1e-3)}
+        del graph
 
     # ---------------- roofline of the dominant kernel of the headline path ----------------
     src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_1609_01797_amd", "csrc", "fused.hip"),

@@ -16,6 +16,18 @@ import sim
 
 PEAK_FP32 = 157.3
 
+_ALPHA_STAR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                           "alpha_star.json")
+
+
+def alpha_star(workload):
+    """The step-size factor alpha of a workload: the one with the lowest
+    vector error rate in the oracle sweep stored in tests/golden/alpha_star.json
+    (written by tests/golden/make_alpha_star.py before any GPU run)."""
+    import json
+    with open(_ALPHA_STAR) as f:
+        return float(json.load(f)["workloads"][workload]["alpha_star"])
+
 
 def loop_flops(N, t_max):
     s2 = N * (N + 1) * (2 * N + 1) // 6
@@ -65,7 +77,7 @@ def run_mixed_workload(args):
     import torch
     import paper_1609_01797_amd as taser
     from paper_1609_01797_amd import autotune
-    V, snr, t_max, alpha = 100000, 12.0, 10, 0.5
+    V, snr, t_max, alpha = 100000, 12.0, 10, alpha_star("mixed")
     d = sim.gen_mixed(V, snr, sim.seed_for(3, snr_index=6))
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -163,7 +175,7 @@ def run_unfolded_workload(args):
     import paper_1609_01797_amd.unfolded as unf
     B, U, mod, batch, t_train = 64, 16, 2, 16384, 20
     N = 2 * U + 1
-    alpha0 = float(getattr(args, "alpha", None) or 0.5)
+    alpha0 = alpha_star("unfolded64x16")
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
@@ -293,11 +305,11 @@ def run_workload(args):
     if args.workload == "unfolded64x16":
         return run_unfolded_workload(args)
     if args.workload == "jed16x16":
-        kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, 0.5
+        kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, alpha_star("jed16x16")
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0], 6.0, 16384
         metric = "detected blocks/s @SIMO JED 16 antennas, 16+1 QPSK slots, t_max=20 (262,144 blocks)"
     else:
-        kind, B, U, mod, V, t_max, alpha = "coh", 32, 8, 2, 1000, 10, 0.5
+        kind, B, U, mod, V, t_max, alpha = "coh", 32, 8, 2, 1000, 10, alpha_star("coherent32x8")
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0], 10.0, 1000
         metric = "detected vectors/s @32x8 QPSK t_max=10 (1,000 vectors, one channel each)"
     N = 2 * U + 1 if mod == 2 else U + 1
