@@ -154,56 +154,33 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
 constexpr int kWsA = 0, kWsC = 1024, kWsD = 1536, kWsDN = 1792, kWsTau = 1856, kWsFlag = 1920;
 constexpr int kWsFloats = 2048;
 
+// Waves (channel groups) per workgroup of the preparation kernel.  Its
+// waves need few registers, so five would fit on a SIMD; four-wave
+// workgroups put one wave on each SIMD of a CU, which keeps a batch of
+// 4 x 1024 groups evenly spread (with one-wave workgroups some SIMDs took
+// five groups and others three, and the kernel lasts as long as the fullest).
+constexpr int kPrepWaves = 4;
+
 // Preprocessing of one channel group (one wave): T~ in bordered form and the
 // step size, stored to the workspace in the register layout of the solve.
-__global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
-  __shared__ float2 Gs[16 * 16];   // G = H^H H, [row][col]
-  __shared__ float2 bs[16 * 16];   // b = H^H y, [user][vector]
-  __shared__ float yy2[16];        // ||y||^2 per vector
+// The complex Gram G = H^H H, b = H^H y and ||y||^2 arrive as MFMA
+// accumulators (lane (n, g) holds rows 4 g + r of column n).
+__device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, const f4& reG,
+                                            const f4& imG, const f4& reb, const f4& imb,
+                                            float ysq) {
+  // one LDS region per wave of the workgroup (each wave is one group)
+  __shared__ float2 Gs_all[kPrepWaves][16 * 16];   // G = H^H H, [row][col]
+  __shared__ float2 bs_all[kPrepWaves][16 * 16];   // b = H^H y, [user][vector]
+  __shared__ float yy2_all[kPrepWaves][16];        // ||y||^2 per vector
 
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15;         // vector within the group (MFMA N index)
   const int g = lane >> 4;         // column quad (MFMA K / output row group)
-  const long long v0 = (long long)blockIdx.x * 16;
-  const long long v = v0 + n;
-  const int B = a.B;
-  const float2* Hg = a.H + (v0 / a.y_per_H) * (long long)B * 16;
-  const float2* yv = a.y + v * B;
+  const long long v = grp * 16 + n;
+  float2* Gs = Gs_all[threadIdx.x >> 6];
+  float2* bs = bs_all[threadIdx.x >> 6];
+  float* yy2 = yy2_all[threadIdx.x >> 6];
 
-  // ---------------- preprocessing: G = H^H H, b = H^H y on MFMA ----------------
-  f4 reG = {0.f, 0.f, 0.f, 0.f}, imG = reG, reb = reG, imb = reG;
-  float ysq = 0.f;
-  // Rows are consumed in batches of 8 row-quads; the next batch's loads are
-  // issued before the current batch's MFMAs so that load latency overlaps.
-  constexpr int kQ = 8;
-  float2 hc[kQ], yc[kQ], hnx[kQ], ynx[kQ];
-  auto load_batch = [&](int r0, float2 (&hb)[kQ], float2 (&yb)[kQ]) {
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const int row = r0 + 4 * q + g;
-      hb[q] = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
-      yb[q] = row < B ? yv[row] : make_float2(0.f, 0.f);
-    }
-  };
-  load_batch(0, hc, yc);
-  for (int r0 = 0; r0 < B; r0 += 4 * kQ) {
-    if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, hnx, ynx);
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const float2 h = hc[q], y = yc[q];
-      reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
-      reG = mfma(h.y, h.y, reG);
-      imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
-      imG = mfma(h.y, -h.x, imG);
-      reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
-      reb = mfma(h.y, y.y, reb);
-      imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
-      imb = mfma(h.y, -y.x, imb);
-      ysq += y.x * y.x + y.y * y.y;
-    }
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) { hc[q] = hnx[q]; yc[q] = ynx[q]; }
-  }
   ysq = sum_groups(ysq);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -211,7 +188,9 @@ __global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
     bs[(4 * g + r) * 16 + n] = make_float2(reb[r], imb[r]);
   }
   if (g == 0) yy2[n] = ysq;
-  __syncthreads();
+  // one wave: its LDS accesses complete in program order; the barrier keeps
+  // the compiler from moving the reads below above the writes
+  __builtin_amdgcn_wave_barrier();
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
   bool bad_group = false, deg_group = false, bad_vec = false, deg_vec = false;
@@ -367,7 +346,7 @@ __global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
     tau = a.alpha / (lam > 0.f ? lam : 1.f);
   }
   // ---------------- hand the group's state to the solve kernel ----------------
-  float* ws = a.ws + (long long)blockIdx.x * kWsFloats;
+  float* ws = a.ws + grp * kWsFloats;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -386,6 +365,57 @@ __global__ __launch_bounds__(64) void prep_group_qpsk16(FusedArgs a) {
   if (g == 0 && a.status)
     a.status[v] = nonfinite ? TASER_VEC_NONFINITE : (degenerate ? TASER_VEC_DEGENERATE : 0);
 }
+
+
+// One row-quad of the channel group: lane (n, g) holds H[4 q + g][n] and
+// y_n[4 q + g]; eight 16x16x4 MFMAs add its share of G and b.
+__device__ __forceinline__ void gram_rowquad(float2 h, float2 y, f4& reG, f4& imG, f4& reb,
+                                             f4& imb, float& ysq) {
+  reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
+  reG = mfma(h.y, h.y, reG);
+  imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
+  imG = mfma(h.y, -h.x, imG);
+  reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
+  reb = mfma(h.y, y.y, reb);
+  imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
+  imb = mfma(h.y, -y.x, imb);
+  ysq += y.x * y.x + y.y * y.y;
+}
+
+// Any B: rows are consumed in batches of 8 row-quads; the next batch's loads
+// are issued before the current batch's MFMAs so that load latency overlaps.
+__global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a, int groups) {
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15;
+  const int g = lane >> 4;
+  const long long grp = (long long)blockIdx.x * kPrepWaves + (threadIdx.x >> 6);
+  if (grp >= groups) return;     // whole waves only; no workgroup barrier follows
+  const int B = a.B;
+  const float2* Hg = a.H + (grp * 16 / a.y_per_H) * (long long)B * 16;
+  const float2* yv = a.y + (grp * 16 + n) * B;
+  f4 reG = {0.f, 0.f, 0.f, 0.f}, imG = reG, reb = reG, imb = reG;
+  float ysq = 0.f;
+  constexpr int kQ = 8;
+  float2 hc[kQ], yc[kQ], hnx[kQ], ynx[kQ];
+  auto load_batch = [&](int r0, float2 (&hb)[kQ], float2 (&yb)[kQ]) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int row = r0 + 4 * q + g;
+      hb[q] = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
+      yb[q] = row < B ? yv[row] : make_float2(0.f, 0.f);
+    }
+  };
+  load_batch(0, hc, yc);
+  for (int r0 = 0; r0 < B; r0 += 4 * kQ) {
+    if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, hnx, ynx);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) gram_rowquad(hc[q], yc[q], reG, imG, reb, imb, ysq);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) { hc[q] = hnx[q]; yc[q] = ynx[q]; }
+  }
+  prep_finish(a, grp, reG, imG, reb, imb, ysq);
+}
+
 
 // Algorithm 1 for one channel group (one wave), from the state the prep
 // kernel left in the workspace.  P selects the arithmetic of the L~ T~
@@ -673,7 +703,9 @@ size_t fused_workspace_bytes(const FusedArgs& a) {
 }
 
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(prep_group_qpsk16, dim3(a.V / 16), dim3(64), 0, s, a);
+  const int groups = a.V / 16;
+  hipLaunchKernelGGL(prep_group_qpsk16, dim3((groups + kPrepWaves - 1) / kPrepWaves),
+                     dim3(64 * kPrepWaves), 0, s, a, groups);
   return hipGetLastError();
 }
 
