@@ -58,22 +58,71 @@ def test_fused_slice_spectral(gpu_lib, snr):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
 
-def test_fused_full_batch_bench_configuration(gpu_lib):
+def _alpha_star():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "alpha_star.json")
+    return float(json.load(open(path))["workloads"]["coherent128x16"]["alpha_star"])
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp32", "bf16", "fp16"])
+def test_fused_full_batch_bench_configuration(gpu_lib, prec):
     """The benchmark's launch: 4,096 channels x 16 vectors, tau spectral,
-    t_max = 10, no L output.  Decisions are checked on a random sample of
+    t_max = 10, the swept alpha, taser_run_prep + taser_run_solve with a
+    workspace, no L output.  Decisions are checked on a random sample of
     2,048 vectors against the oracle; L~ on the same sample from a second
     launch that also writes L~."""
+    import torch
+    alpha = _alpha_star()
     d = sim.gen_mimo(B, U, oracle.QPSK, 4096, YPH, 10.0, sim.seed_for(2, snr_index=5))
     V = 4096 * YPH
-    desc = gpu_lib.make_desc(V, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=0.5)
-    g = fused(gpu_lib, desc, d["H"], d["y"], want_L=False)
+    desc = gpu_lib.make_desc(V, B, U, oracle.QPSK, prec=prec, y_per_H=YPH, t_max=10, alpha=alpha)
+    H, y = _cuda(d["H"]), _cuda(d["y"])
+    ws = torch.empty(gpu_lib.workspace_size(desc), dtype=torch.uint8, device="cuda")
+    out = gpu_lib.run_prep(desc, H, y, ws=ws)
+    out = gpu_lib.run_solve(desc, out, ws=ws)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
     idx = np.sort(np.random.default_rng(7).choice(V, size=2048, replace=False))
-    ref = _group_oracle(d, 0.5, 10, idx=idx)
-    assert_decisions(g["sbar"][idx], ref["sbar"], ref["margin"])
+    ref = _group_oracle(d, alpha, 10, idx=idx)
+    ltol, mtol = (1e-5, 1e-4) if prec == 0 else PREC_TOL[prec]
+    assert_decisions(g["sbar"][idx], ref["sbar"], ref["margin"], tol=mtol)
     assert np.all(g["status"] == 0)
     g2 = fused(gpu_lib, desc, d["H"], d["y"], want_L=True)
     np.testing.assert_array_equal(g2["sbar"], g["sbar"])
-    assert_L_parity(unpack_lower(g2["L"][idx], N), ref["L"])
+    assert_L_parity(unpack_lower(g2["L"][idx], N), ref["L"], tol=ltol)
+
+
+def test_fused_graph_replay(gpu_lib):
+    """taser_run_prep + taser_run_solve captured once in a HIP graph (as the
+    benchmark replays them): every replay, with eager work and
+    synchronisations in between, reproduces the eager result bit for bit."""
+    import torch
+    d = sim.gen_mimo(B, U, oracle.QPSK, 256, YPH, 2.0, sim.seed_for(2, snr_index=6))
+    V = 256 * YPH
+    H, y = _cuda(d["H"]), _cuda(d["y"])
+    for prec in (0, 1):
+        desc = gpu_lib.make_desc(V, B, U, oracle.QPSK, prec=prec, y_per_H=YPH, t_max=10, alpha=0.9)
+        ws = torch.empty(gpu_lib.workspace_size(desc), dtype=torch.uint8, device="cuda")
+        eager = gpu_lib.run_solve(desc, gpu_lib.run_prep(desc, H, y, ws=ws), want_margin=True, ws=ws)
+        eager = {k: v.clone() for k, v in eager.items()}
+        out = {k: torch.empty_like(v) for k, v in eager.items()}
+        gpu_lib.run_solve(desc, gpu_lib.run_prep(desc, H, y, out=out, ws=ws), want_margin=True, ws=ws)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gpu_lib.run_prep(desc, H, y, out=out, ws=ws)
+            gpu_lib.run_solve(desc, out, want_margin=True, ws=ws)
+        for rep in range(4):
+            for v in out.values():
+                v.zero_()
+            ws.zero_()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            for k in eager:
+                assert torch.equal(out[k], eager[k]), (prec, rep, k)
+        del graph
 
 
 def test_fused_degenerate_groups(gpu_lib):
