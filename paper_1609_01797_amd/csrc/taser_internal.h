@@ -76,18 +76,6 @@ struct UnfoldedArgs {
   int32_t V, N, t_max, real, ckpt_every, flags;
 };
 size_t unfolded_lds_bytes(const UnfoldedArgs& a);
-// LDS bytes of `states` N x N states stored NP x NP, NP = N rounded up to 8.
-inline size_t unfolded_lds_states(int N, int states, size_t elem) {
-  const size_t NS = (size_t)((N + 7) & ~7);
-  return (size_t)states * NS * NS * elem;
-}
-// Per register bucket NP (multiple of 8, >= N); instantiated for float and double.
-template <int NP, typename Real>
-hipError_t unf_fwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
-                   const void* alpha, void* ckpt, void* Lout, hipStream_t s);
-template <int NP, typename Real>
-hipError_t unf_bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
-                   const void* alpha, const void* ckpt, const void* dL, void* ws, hipStream_t s);
 size_t unfolded_workspace_bytes(const UnfoldedArgs& a);
 hipError_t launch_unfolded_forward(const UnfoldedArgs& a, const void* Tt, const void* D,
                                    const void* lam, const void* alpha, void* ckpt, void* Lout,
@@ -95,6 +83,27 @@ hipError_t launch_unfolded_forward(const UnfoldedArgs& a, const void* Tt, const 
 hipError_t launch_unfolded_backward(const UnfoldedArgs& a, const void* Tt, const void* D,
                                     const void* lam, const void* alpha, const void* ckpt,
                                     const void* dL, void* dalpha, void* ws, hipStream_t s);
+// LDS bytes of `states` states of an N x N lower-triangular matrix stored as
+// packed rows, row i padded to 4 * floor((i + 4) / 4) entries.
+inline size_t unfolded_lds_states(int N, int states, size_t elem) {
+  size_t s = 0;
+  for (int r = 0; r < N; ++r) s += 4 * (size_t)((r + 4) / 4);
+  return (size_t)states * s * elem;
+}
+// Vectors per wave of the unfolded kernels: two when every column that
+// changes fits in 32 lanes (N <= 32, or N = 33 with L~_NN held), float only.
+inline int unfolded_vectors_per_wave(const UnfoldedArgs& a) {
+  const bool pin = !(a.flags & TASER_FLAG_LITERAL_LAST);
+  return a.real == 0 && (a.N <= 32 || (a.N == 33 && pin)) ? 2 : 1;
+}
+// Per register bucket NP (multiple of 8, >= N) and vectors per wave HV;
+// instantiated for float (HV = 1, 2) and double (HV = 1).
+template <int NP, int HV, typename Real>
+hipError_t unf_fwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
+                   const void* alpha, void* ckpt, void* Lout, hipStream_t s);
+template <int NP, int HV, typename Real>
+hipError_t unf_bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
+                   const void* alpha, const void* ckpt, const void* dL, void* ws, hipStream_t s);
 
 // LDS bytes the staged build kernel needs (0 if the shape does not fit).
 size_t build_T_lds_bytes(int B, int U, int N);

@@ -43,7 +43,12 @@ template <typename Real>
 hipError_t fwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
                const void* alpha, void* ckpt, void* Lout, hipStream_t s) {
   return dispatch(a.N, [&](auto np) {
-    return unf_fwd<decltype(np)::value, Real>(a, Tt, D, lam, alpha, ckpt, Lout, s);
+    constexpr int NP = decltype(np)::value;
+    if constexpr (sizeof(Real) == 4 && NP <= 40) {
+      if (unfolded_vectors_per_wave(a) == 2)
+        return unf_fwd<NP, 2, Real>(a, Tt, D, lam, alpha, ckpt, Lout, s);
+    }
+    return unf_fwd<NP, 1, Real>(a, Tt, D, lam, alpha, ckpt, Lout, s);
   });
 }
 
@@ -52,7 +57,12 @@ hipError_t bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void*
                const void* alpha, const void* ckpt, const void* dL, void* dalpha, void* ws,
                hipStream_t s) {
   hipError_t e = dispatch(a.N, [&](auto np) {
-    return unf_bwd<decltype(np)::value, Real>(a, Tt, D, lam, alpha, ckpt, dL, ws, s);
+    constexpr int NP = decltype(np)::value;
+    if constexpr (sizeof(Real) == 4 && NP <= 40) {
+      if (unfolded_vectors_per_wave(a) == 2)
+        return unf_bwd<NP, 2, Real>(a, Tt, D, lam, alpha, ckpt, dL, ws, s);
+    }
+    return unf_bwd<NP, 1, Real>(a, Tt, D, lam, alpha, ckpt, dL, ws, s);
   });
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(unf_reduce<Real>, dim3(a.t_max), dim3(256), 0, s, a.V, a.t_max,
@@ -63,8 +73,8 @@ hipError_t bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void*
 }  // namespace
 
 size_t unfolded_lds_bytes(const UnfoldedArgs& a) {
-  return a.real == 1 ? unfolded_lds_states(a.N, a.ckpt_every + 1, 8)
-                     : unfolded_lds_states(a.N, a.ckpt_every + 1, 4);
+  return unfolded_lds_states(a.N, (a.ckpt_every + 1) * unfolded_vectors_per_wave(a),
+                             a.real == 1 ? 8 : 4);
 }
 
 size_t unfolded_workspace_bytes(const UnfoldedArgs& a) {

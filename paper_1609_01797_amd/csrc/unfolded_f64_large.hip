@@ -3,15 +3,15 @@
 
 namespace taser {
 
-template hipError_t unf_fwd<56, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, void*, void*, hipStream_t);
-template hipError_t unf_bwd<56, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, const void*, const void*,
-                                        void*, hipStream_t);
-template hipError_t unf_fwd<64, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, void*, void*, hipStream_t);
-template hipError_t unf_bwd<64, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, const void*, const void*,
-                                        void*, hipStream_t);
+template hipError_t unf_fwd<56, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<56, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, const void*, const void*,
+                                           void*, hipStream_t);
+template hipError_t unf_fwd<64, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<64, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, const void*, const void*,
+                                           void*, hipStream_t);
 
 }  // namespace taser

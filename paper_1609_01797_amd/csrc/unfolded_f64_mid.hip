@@ -3,15 +3,15 @@
 
 namespace taser {
 
-template hipError_t unf_fwd<40, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, void*, void*, hipStream_t);
-template hipError_t unf_bwd<40, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, const void*, const void*,
-                                        void*, hipStream_t);
-template hipError_t unf_fwd<48, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, void*, void*, hipStream_t);
-template hipError_t unf_bwd<48, double>(const UnfoldedArgs&, const void*, const void*,
-                                        const void*, const void*, const void*, const void*,
-                                        void*, hipStream_t);
+template hipError_t unf_fwd<40, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<40, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, const void*, const void*,
+                                           void*, hipStream_t);
+template hipError_t unf_fwd<48, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, void*, void*, hipStream_t);
+template hipError_t unf_bwd<48, 1, double>(const UnfoldedArgs&, const void*, const void*,
+                                           const void*, const void*, const void*, const void*,
+                                           void*, hipStream_t);
 
 }  // namespace taser

@@ -169,3 +169,22 @@ def test_training_lowers_loss(gpu_lib, unf):
     after = test_loss()
     assert torch.isfinite(alpha).all()
     assert after < 0.9 * before, (before, after)
+
+
+@pytest.mark.parametrize("B,U,mod,V,literal", [
+    (64, 16, oracle.QPSK, 25, False),   # N = 33, two vectors per wave, odd batch (one idle half)
+    (32, 8, oracle.QPSK, 31, True),     # N = 17, two vectors per wave, literal L~_NN
+    (48, 40, oracle.BPSK, 7, False),    # N = 41, one vector per wave
+])
+def test_fp32_layouts_forward_and_gradient(gpu_lib, unf, B, U, mod, V, literal):
+    """FP32 forward and gradient against the FP64 oracle for the wave
+    layouts the kernels choose between (two vectors per wave with an idle
+    half, literal last column, one vector per wave)."""
+    import torch
+    Tt, D, lam, sbar = problem(B, U, mod, V, 1.0, sim.seed_for(46, V))
+    alpha = np.linspace(0.4, 0.9, 6)
+    L_ref, loss_ref, g_ref = oracle_grad(Tt, D, lam, alpha, sbar, pin_last=not literal)
+    L, loss, g = gpu_grad(gpu_lib, unf, Tt, D, lam, alpha, sbar, torch.float32, literal_last=literal)
+    assert np.max(rel_frobenius(L, L_ref)) <= L_REL_TOL
+    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
+    assert np.max(np.abs(g - g_ref)) <= 1e-3 * np.max(np.abs(g_ref)), (g, g_ref)
