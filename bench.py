@@ -236,21 +236,28 @@ def main():
             taser.run_prep(desc, H, y, out=out, ws=ws)
             taser.run_solve(desc, out, ws=ws)
         torch.cuda.synchronize()
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0.record(stream)
         for k in range(args.steps):
-            ev[k][0].record(stream)
             taser.run_prep(desc, H, y, out=out, ws=ws)
-            ev[k][1].record(stream)
             taser.run_solve(desc, out, ws=ws)
-            ev[k][2].record(stream)
         t1.record(stream)
         torch.cuda.synchronize()
         ms_step = t0.elapsed_time(t1) / args.steps
-        prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-        solve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        # each kernel on its own: the same number of launches back to back
+        # between two events on the launch stream (the per-launch event pairs
+        # above also count the gaps between launches)
+        def per_launch(fn):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps
+        prep_ms = per_launch(lambda: taser.run_prep(desc, H, y, out=out, ws=ws))
+        solve_ms = per_launch(lambda: taser.run_solve(desc, out, ws=ws))
         timing[name] = {"ms_per_step": ms_step, "vectors_per_s": V / (ms_step * 1e-3),
                         "prep_kernel_ms": prep_ms, "solve_kernel_ms": solve_ms,
                         "status_nonzero": int(torch.count_nonzero(out["status"]).item())}
