@@ -137,18 +137,11 @@ __device__ __forceinline__ float top_eigenvalue(const float (&al)[M], const floa
   return 0.5f * (lo + hi);
 }
 
-// Largest number of T entries a lane accumulates: U(U+1)/2 Gram pairs, U
-// matched-filter entries and ||y||^2, spread over 64 lanes, for U <= 32.
-constexpr int kEntriesPerLane = 9;
-constexpr int kChunk = 32;   // channel rows staged in LDS per pass
-
 template <int NT>
 struct VecLds {
   static constexpr int N1 = 16 * NT;
-  static constexpr int UMAX = N1 < 32 ? N1 : 32;                 // largest U for this tile count
   static constexpr int TT = (N1 + 1) * (N1 + 1);                 // padded T
-  static constexpr int STAGE = kChunk * (UMAX + 1) * 2;          // rows x (U + y) complex
-  static constexpr int REGION = TT > STAGE ? TT : STAGE;
+  static constexpr int REGION = TT;
   static constexpr int FLOATS = REGION + (N1 + 1) + N1;          // + D + shuffle buffer
 };
 
@@ -170,7 +163,6 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
   float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
-  float2* stage = reinterpret_cast<float2*>(lds);  // aliases T while the Gram is accumulated
   float* Dl = lds + S::REGION;           // [N1+1]
   float* sh = Dl + (N1 + 1);             // [N1] layout shuffle
 
@@ -184,95 +176,123 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   const float sg = jed ? -1.f : 1.f;
 
   // ---------------- preprocessing: complex Gram, H^H y, ||y||^2 ----------------
-  const int n_pairs = U * (U + 1) / 2;
-  const int n_entries = n_pairs + U + 1;
-  int ep[kEntriesPerLane], eq[kEntriesPerLane];
-#pragma unroll
-  for (int k = 0; k < kEntriesPerLane; ++k) {
-    const int e = lane + 64 * k;
-    int p = -1, q = -1;
-    if (e < n_pairs) {
-      p = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
-      while (p * (p + 1) / 2 > e) --p;
-      while ((p + 1) * (p + 2) / 2 <= e) ++p;
-      q = e - p * (p + 1) / 2;
-    } else if (e < n_pairs + U) {
-      p = e - n_pairs;
-      q = U;                                   // column U of the stage = y
-    } else if (e < n_entries) {
-      p = U;
-      q = U;
-    }
-    ep[k] = p;
-    eq[k] = q;
-  }
-  float are[kEntriesPerLane], aim[kEntriesPerLane];
-#pragma unroll
-  for (int k = 0; k < kEntriesPerLane; ++k) { are[k] = 0.f; aim[k] = 0.f; }
-  const int W = U + 1;                         // stage row width (complex)
+  // G = H^H H on 16x16x4 MFMAs, streamed from HBM: for row-quad q, lane
+  // (n, g) holds h_t = H[4 q + g][16 t + n] (user tile t); Re G and Im G of
+  // user tiles (t1, t2) accumulate from h_t1 (A) and h_t2 (B), only t1 >= t2
+  // (G is Hermitian).  H^H y and ||y||^2 are lane partial sums over the
+  // lane's rows, reduced over the four row lanes afterwards.  For joint
+  // detection H is Y_r = [y_1 .. y_K] and y is y_0 s_0.
+  constexpr int UTM = NT >= 2 ? 2 : 1;         // user tiles (U <= 16 NT, U <= 32)
+  const int UT = U > 16 ? 2 : 1;
   const float2* Hg = job.H;
   const float2* yg = job.y;
   const float2 s0 = job.s0;
-  for (int b0 = 0; b0 < B; b0 += kChunk) {
-    const int rows = min(kChunk, B - b0);
-    for (int e = lane; e < rows * W; e += 64) {
-      const int r = e / W, c = e - r * W;
-      const int b = b0 + r;
-      float2 x;
-      if (!jed) {
-        x = c < U ? Hg[(long long)b * U + c] : yg[b];
-      } else if (c < U) {
-        x = yg[(long long)(c + 1) * B + b];    // Y_r: slots 1..K
-      } else {
-        const float2 y0 = yg[b];                // y_0 s_0
-        x = make_float2(y0.x * s0.x - y0.y * s0.y, y0.x * s0.y + y0.y * s0.x);
-      }
-      stage[r * W + c] = x;
-    }
-    __syncthreads();
+  auto hval = [&](int row, int u) {
+    if (row >= B || u >= U) return make_float2(0.f, 0.f);
+    return jed ? yg[(long long)(u + 1) * B + row] : Hg[(long long)row * U + u];
+  };
+  auto yval = [&](int row) {
+    if (row >= B) return make_float2(0.f, 0.f);
+    const float2 y0 = yg[row];
+    if (!jed) return y0;
+    return make_float2(y0.x * s0.x - y0.y * s0.y, y0.x * s0.y + y0.y * s0.x);
+  };
+  f4 gre[3], gim[3];                           // tiles (0,0), (1,0), (1,1)
 #pragma unroll
-    for (int k = 0; k < kEntriesPerLane; ++k) {
-      if (ep[k] >= 0) {
-        float re = are[k], im = aim[k];
-#pragma unroll 2
-        for (int r = 0; r < rows; ++r) {
-          const float2 hp = stage[r * W + ep[k]];
-          const float2 hq = stage[r * W + eq[k]];
-          re += hp.x * hq.x + hp.y * hq.y;     // conj(h_p) h_q
-          im += hp.x * hq.y - hp.y * hq.x;
-        }
-        are[k] = re;
-        aim[k] = im;
-      }
+  for (int k = 0; k < 3; ++k) { gre[k] = f4{0.f, 0.f, 0.f, 0.f}; gim[k] = gre[k]; }
+  float bre[UTM], bim[UTM], ysq = 0.f;
+#pragma unroll
+  for (int t = 0; t < UTM; ++t) { bre[t] = 0.f; bim[t] = 0.f; }
+  constexpr int kQ = 4;                        // row-quads per batch (double-buffered)
+  float2 hc[kQ][UTM], yc[kQ], hn[kQ][UTM], yn[kQ];
+  auto load_batch = [&](int q0, float2 (&hb)[kQ][UTM], float2 (&yb)[kQ]) {
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int row = 4 * (q0 + q) + g;
+#pragma unroll
+      for (int t = 0; t < UTM; ++t) hb[q][t] = t < UT ? hval(row, 16 * t + n) : make_float2(0.f, 0.f);
+      yb[q] = yval(row);
     }
-    __syncthreads();
+  };
+  const int quads = (B + 3) / 4;
+  load_batch(0, hc, yc);
+  for (int q0 = 0; q0 < quads; q0 += kQ) {
+    if (q0 + kQ < quads) load_batch(q0 + kQ, hn, yn);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const float2 h0 = hc[q][0], y = yc[q];
+      gre[0] = mfma(h0.x, h0.x, gre[0]);       // Re G = Hr^T Hr + Hi^T Hi
+      gre[0] = mfma(h0.y, h0.y, gre[0]);
+      gim[0] = mfma(h0.x, h0.y, gim[0]);       // Im G = Hr^T Hi - Hi^T Hr
+      gim[0] = mfma(h0.y, -h0.x, gim[0]);
+      if constexpr (UTM == 2) {
+        if (UT == 2) {
+          const float2 h1 = hc[q][1];
+          gre[1] = mfma(h1.x, h0.x, gre[1]);
+          gre[1] = mfma(h1.y, h0.y, gre[1]);
+          gim[1] = mfma(h1.x, h0.y, gim[1]);
+          gim[1] = mfma(h1.y, -h0.x, gim[1]);
+          gre[2] = mfma(h1.x, h1.x, gre[2]);
+          gre[2] = mfma(h1.y, h1.y, gre[2]);
+          gim[2] = mfma(h1.x, h1.y, gim[2]);
+          gim[2] = mfma(h1.y, -h1.x, gim[2]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < UTM; ++t) {          // conj(h) y
+        bre[t] = fmaf(hc[q][t].x, y.x, fmaf(hc[q][t].y, y.y, bre[t]));
+        bim[t] = fmaf(hc[q][t].x, y.y, fmaf(-hc[q][t].y, y.x, bim[t]));
+      }
+      ysq = fmaf(y.x, y.x, fmaf(y.y, y.y, ysq));
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      yc[q] = yn[q];
+#pragma unroll
+      for (int t = 0; t < UTM; ++t) hc[q][t] = hn[q][t];
+    }
   }
+#pragma unroll
+  for (int t = 0; t < UTM; ++t) { bre[t] = sum_quads(bre[t]); bim[t] = sum_quads(bim[t]); }
+  ysq = sum_quads(ysq);                        // rows 4 q + g summed over the four g lanes
+
   // T in padded indexing (eq. (2) coherent, eq. (5) joint detection)
   for (int e = lane; e < S::TT; e += 64) T[e] = 0.f;
   __syncthreads();
   constexpr int LD = N1 + 1;
+  auto put_tile = [&](const f4& re4, const f4& im4, int t1, int t2) {
 #pragma unroll
-  for (int k = 0; k < kEntriesPerLane; ++k) {
-    const int p = ep[k], q = eq[k];
-    if (p < 0) continue;
-    if (p < U && q < U) {
-      const float gre = sg * are[k], gim = sg * aim[k];
+    for (int r = 0; r < 4; ++r) {
+      const int p = 16 * t1 + 4 * g + r, q = 16 * t2 + n;
+      if (p >= U || q >= U) continue;
+      const float gr = sg * re4[r], gi = p == q ? 0.f : sg * im4[r];
       if (qpsk) {
-        T[p * LD + q] = gre; T[q * LD + p] = gre;
-        T[(U + p) * LD + U + q] = gre; T[(U + q) * LD + U + p] = gre;
-        T[p * LD + U + q] = -gim; T[(U + q) * LD + p] = -gim;
-        if (p != q) { T[q * LD + U + p] = gim; T[(U + p) * LD + q] = gim; }
+        T[p * LD + q] = gr; T[q * LD + p] = gr;
+        T[(U + p) * LD + U + q] = gr; T[(U + q) * LD + U + p] = gr;
+        T[p * LD + U + q] = -gi; T[(U + q) * LD + p] = -gi;
+        T[q * LD + U + p] = gi; T[(U + p) * LD + q] = gi;
       } else {
-        T[p * LD + q] = gre; T[q * LD + p] = gre;
+        T[p * LD + q] = gr; T[q * LD + p] = gr;
       }
-    } else if (p < U) {
-      // last column: -Hbar^T ybar in both modes
-      T[p * LD + N1] = -are[k]; T[N1 * LD + p] = -are[k];
-      if (qpsk) { T[(U + p) * LD + N1] = -aim[k]; T[N1 * LD + U + p] = -aim[k]; }
-    } else {
-      T[N1 * LD + N1] = sg * are[k];
+    }
+  };
+  put_tile(gre[0], gim[0], 0, 0);
+  if (UT == 2) {
+    put_tile(gre[1], gim[1], 1, 0);
+    put_tile(gre[2], gim[2], 1, 1);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int t = 0; t < UTM; ++t) {
+      const int p = 16 * t + n;
+      if (p < U) {
+        // last column: -Hbar^T ybar in both modes
+        T[p * LD + N1] = -bre[t]; T[N1 * LD + p] = -bre[t];
+        if (qpsk) { T[(U + p) * LD + N1] = -bim[t]; T[N1 * LD + U + p] = -bim[t]; }
+      }
     }
   }
+  if (lane == 0) T[N1 * LD + N1] = sg * ysq;
   __syncthreads();
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
