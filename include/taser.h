@@ -186,7 +186,7 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
    (complex64 B_v x U_v row-major, starting H_off[v] complex elements into H)
    and receive vector (B_v complex64 at y + y_off[v]).  The call sorts the
    vectors into size buckets on the device (N-1 <= 16, <= 32, <= 64) and runs
-   one persistent kernel per bucket; it allocates nothing, synchronises
+   one kernel per bucket; it allocates nothing, synchronises
    nothing and launches a fixed sequence of kernels (capturable into a HIP
    graph).  desc->num_vectors, prec, tau_mode, t_max, flags and alpha apply to
    every vector; desc->mode must be TASER_COHERENT; desc->B, U, mod and
@@ -194,8 +194,11 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
    [V][stride] (or NULL): the first N_v - 1 entries of row v are the
    decisions / margins, the rest of the row is 0; status [V].  Vectors with U_v > 32 or N_v - 1 > 64 get status
    TASER_VEC_UNSUPPORTED.  All per-vector arrays are device arrays. */
+/* Grid per size bucket: 0 (the default) launches one workgroup per vector of
+   the batch, those past the bucket's count exit at once; n > 0 launches a
+   persistent grid of n workgroups that walk the bucket's list.  NULL = all 0. */
 typedef struct {
-  int32_t blocks[3];    /* persistent blocks per bucket; 0 = library default */
+  int32_t blocks[3];
 } taser_mixed_launch_t;
 
 taser_status_t taser_mixed_workspace_size(const taser_desc_t* desc, size_t* bytes);

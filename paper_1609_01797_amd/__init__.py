@@ -47,7 +47,8 @@ class Desc(ctypes.Structure):
 
 
 class MixedLaunch(ctypes.Structure):
-    """Persistent blocks per size bucket (N-1 <= 16, <= 32, <= 64); 0 = default."""
+    """Grid per size bucket (N-1 <= 16, <= 32, <= 64): 0 = one workgroup per
+    vector (default), n > 0 = persistent grid of n workgroups."""
     _fields_ = [("blocks", ctypes.c_int32 * 3)]
 
 
@@ -348,7 +349,7 @@ def run_mixed(desc: Desc, Bv, Uv, modv, H_off, y_off, H, y, tau=None, want_margi
               blocks=None, out=None, ws=None):
     """Mixed-size coherent batch in one call (``taser_run_mixed``).
     Bv, Uv, modv: int32 [V]; H_off, y_off: int64 [V] (complex elements);
-    H, y: flat complex64 device tensors.  ``blocks``: persistent blocks per
+    H, y: flat complex64 device tensors.  ``blocks``: grid per
     bucket (3 ints, 0 = default), e.g. from the autotuner.  Returns dict with
     sbar int8 [V, 64] (first N_v - 1 entries valid), status (+ margin)."""
     torch = _torch()

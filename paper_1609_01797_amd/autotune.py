@@ -1,9 +1,11 @@
 """Launch-configuration autotuner for the mixed-size batch path.
 
-The tunable knob is the persistent grid of each size bucket (N-1 <= 16,
-<= 32, <= 64): how many one-wave blocks walk the bucket's vector list.  Too
-few leave compute units idle; too many cost scheduling overhead and the
-tail.  ``tune_mixed`` times candidate grids on the device for one bucket at
+The tunable knob is the grid of each size bucket (N-1 <= 16, <= 32, <= 64):
+0 = one one-wave workgroup per vector of the batch (the library default),
+n > 0 = a persistent grid of n workgroups walking the bucket's vector list.
+The persistent kernel saves workgroup launches but carries its loop's state
+in registers; which wins depends on the bucket and the batch.
+``tune_mixed`` times candidate grids on the device for one bucket at
 a time (coordinate descent, the other buckets at their current best), keeps
 the fastest, and caches the result in a JSON file keyed by GPU architecture,
 bucket, precision and t_max.  Timing uses HIP events on the launch stream.
@@ -15,7 +17,7 @@ import os
 import threading
 
 _LOCK = threading.Lock()
-CANDIDATES = (512, 1024, 2048, 4096, 8192, 16384)
+CANDIDATES = (0, 1024, 2048, 4096, 8192, 16384)
 DEFAULT_CACHE = os.environ.get("TASER_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "taser_autotune.json"))
 

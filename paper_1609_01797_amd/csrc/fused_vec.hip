@@ -666,13 +666,22 @@ __global__ __launch_bounds__(64) void fused_vec_mixed(FusedArgs a, MixedArgs m, 
   __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
   const int count = m.count[bucket];
   const int32_t* list = m.list + (long long)bucket * a.V;
+  // The job's sizes and offsets are the same in every lane: moving them to
+  // scalar registers keeps the sizes, loop bounds and pointers of the body
+  // out of the vector registers (the loads below are vector loads).
+  auto uni = [](int x) { return __builtin_amdgcn_readfirstlane(x); };
+  auto uni64 = [&](long long x) {
+    const unsigned lo = (unsigned)uni((int)(x & 0xffffffffll));
+    const unsigned hi = (unsigned)uni((int)(x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+  };
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
     VecJob job;
-    job.v = list[item];
-    job.B = m.Bv[job.v]; job.U = m.Uv[job.v]; job.mod = m.modv[job.v];
+    job.v = uni(list[item]);
+    job.B = uni(m.Bv[job.v]); job.U = uni(m.Uv[job.v]); job.mod = uni(m.modv[job.v]);
     job.N = job.mod == TASER_QPSK ? 2 * job.U + 1 : job.U + 1;
-    job.H = a.H + m.H_off[job.v];
-    job.y = a.y + m.y_off[job.v];
+    job.H = a.H + uni64(m.H_off[job.v]);
+    job.y = a.y + uni64(m.y_off[job.v]);
     job.s0 = make_float2(1.f, 0.f);
     job.sbar = a.sbar + job.v * (long long)m.stride;
     job.margin = a.margin ? a.margin + job.v * (long long)m.stride : nullptr;
@@ -681,6 +690,30 @@ __global__ __launch_bounds__(64) void fused_vec_mixed(FusedArgs a, MixedArgs m, 
     vec_body<NT, P>(a, job, lds);
     __syncthreads();   // the next vector reuses the LDS
   }
+}
+
+// Mixed-size batch, one workgroup per entry of the batch: workgroup i takes
+// entry i of the bucket's list and those past the bucket's count exit at
+// once.  Without the persistent loop the body keeps its registers to itself
+// (the loop made the compiler keep loop-invariant index arithmetic live
+// through every vector: 198 instead of 107 VGPRs for N-1 <= 32).
+template <int NT, int P>
+__global__ __launch_bounds__(64) void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
+  __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
+  const int item = blockIdx.x;
+  if (item >= m.count[bucket]) return;
+  VecJob job;
+  job.v = m.list[(long long)bucket * a.V + item];
+  job.B = m.Bv[job.v]; job.U = m.Uv[job.v]; job.mod = m.modv[job.v];
+  job.N = job.mod == TASER_QPSK ? 2 * job.U + 1 : job.U + 1;
+  job.H = a.H + m.H_off[job.v];
+  job.y = a.y + m.y_off[job.v];
+  job.s0 = make_float2(1.f, 0.f);
+  job.sbar = a.sbar + job.v * (long long)m.stride;
+  job.margin = a.margin ? a.margin + job.v * (long long)m.stride : nullptr;
+  job.L = nullptr;
+  job.pad_to = m.stride;
+  vec_body<NT, P>(a, job, lds);
 }
 
 // Size bucket of a mixed-batch vector: 0 = N-1 <= 16, 1 = <= 32, 2 = <= 64,
@@ -735,15 +768,28 @@ __global__ void mixed_assign(FusedArgs a, MixedArgs m) {
   }
 }
 
+// blocks > 0: a persistent grid of that many workgroups; 0: one workgroup
+// per entry of the batch (the default).
 template <int NT>
 bool launch_mixed_nt(const FusedArgs& a, const MixedArgs& m, int bucket, int blocks, hipStream_t s) {
-  const dim3 grid(blocks), block(64);
-  if (a.prec == TASER_PREC_BF16)
-    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_BF16>), grid, block, 0, s, a, m, bucket);
-  else if (a.prec == TASER_PREC_F16)
-    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
-  else
-    hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+  const dim3 block(64);
+  if (blocks > 0) {
+    const dim3 grid(blocks);
+    if (a.prec == TASER_PREC_BF16)
+      hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_BF16>), grid, block, 0, s, a, m, bucket);
+    else if (a.prec == TASER_PREC_F16)
+      hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
+    else
+      hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+  } else {
+    const dim3 grid(a.V);
+    if (a.prec == TASER_PREC_BF16)
+      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_BF16>), grid, block, 0, s, a, m, bucket);
+    else if (a.prec == TASER_PREC_F16)
+      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
+    else
+      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+  }
   return true;
 }
 
@@ -765,17 +811,11 @@ size_t mixed_workspace_bytes(int V) {
   return 256 + (size_t)kMixedBuckets * (size_t)V * sizeof(int32_t);
 }
 
-int mixed_default_blocks(int bucket) {
-  // persistent grid: blocks per launch for N-1 <= 16, <= 32, <= 64
-  static const int k[kMixedBuckets] = {8192, 4096, 1024};
-  return k[bucket];
-}
-
 hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s) {
   hipLaunchKernelGGL(mixed_clear, dim3(1), dim3(64), 0, s, m.count);
   hipLaunchKernelGGL(mixed_assign, dim3((a.V + 255) / 256), dim3(256), 0, s, a, m);
   for (int b = 0; b < kMixedBuckets; ++b) {
-    const int g = blocks && blocks[b] > 0 ? blocks[b] : mixed_default_blocks(b);
+    const int g = blocks ? blocks[b] : 0;
     if (b == 0) launch_mixed_nt<1>(a, m, b, g, s);
     if (b == 1) launch_mixed_nt<2>(a, m, b, g, s);
     if (b == 2) launch_mixed_nt<4>(a, m, b, g, s);

@@ -68,7 +68,6 @@ struct MixedArgs {
   int32_t* list;
 };
 size_t mixed_workspace_bytes(int V);
-int mixed_default_blocks(int bucket);
 hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s);
 
 // Unfolded variant (per-iteration step sizes) and its adjoint.

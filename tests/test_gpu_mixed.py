@@ -82,7 +82,7 @@ def test_mixed_launch_configs_agree(gpu_lib, mixed_case):
     ins = _inputs(d)
     base = gpu_lib.run_mixed(desc, *ins, want_margin=True)
     base = {k: v.clone() for k, v in base.items()}
-    for blocks in ([1, 1, 1], [7, 3, 2], [4096, 4096, 4096]):
+    for blocks in ([1, 1, 1], [7, 3, 2], [0, 5, 0], [4096, 4096, 4096]):
         r = gpu_lib.run_mixed(desc, *ins, want_margin=True, blocks=blocks)
         torch.cuda.synchronize()
         for k in ("sbar", "margin", "status"):
