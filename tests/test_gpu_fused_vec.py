@@ -91,6 +91,29 @@ def test_vec_jed_16bit(gpu_lib, prec):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=mtol)
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_vec_jed_full_batch_bench_configuration(gpu_lib, prec):
+    """The benchmark's joint-detection launch: 262,144 blocks, B = 16,
+    K = 16 + pilot, t_max = 20, the swept alpha, tau spectral.  Decisions are
+    checked against the oracle on 2,048 sampled blocks."""
+    import json
+    import os
+    alpha = float(json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alpha_star.json")))
+                  ["workloads"]["jed16x16"]["alpha_star"])
+    nb = 262144
+    d = sim.gen_jed(16, 16, oracle.QPSK, nb, 4.0, sim.seed_for(5, snr_index=2))
+    desc = gpu_lib.make_desc(nb, 16, 16, oracle.QPSK, mode=gpu_lib.JED, prec=prec, t_max=20, alpha=alpha)
+    import torch
+    res = gpu_lib.run(desc, None, _cuda(d["Y"]), _cuda(d["s0"]))
+    torch.cuda.synchronize()
+    sb, st = res["sbar"].cpu().numpy(), res["status"].cpu().numpy()
+    assert np.all(st == 0)
+    idx = np.sort(np.random.default_rng(13).choice(nb, size=2048, replace=False))
+    ref = oracle.detect_jed(d["Y"][idx], d["s0"][idx], oracle.QPSK, alpha=alpha, t_max=20)
+    mtol = 1e-4 if prec == 0 else PREC_TOL[prec][1]
+    assert_decisions(sb[idx], ref["sbar"], ref["margin"], tol=mtol)
+
+
 def test_vec_degenerate_and_flags(gpu_lib):
     B, U, mod = 32, 8, oracle.QPSK
     d = sim.gen_mimo(B, U, mod, 8, 1, 5.0, 8181)

@@ -137,3 +137,39 @@ def test_mixed_unsupported_sizes(gpu_lib):
     sb = res["sbar"].cpu().numpy()
     assert np.all(sb[big][:, :64] == 1)          # N - 1 = 80 > stride: the whole row is +1
     assert np.all(sb[~big][:, 16:] == 0)         # padding past N - 1 = 16 is 0
+
+
+def _alpha_star(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "alpha_star.json")
+    return float(json.load(open(path))["workloads"][name]["alpha_star"])
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
+def test_mixed_full_batch_bench_configuration(gpu_lib, prec):
+    """The benchmark's mixed launch: 100,000 vectors over the six classes,
+    SNR 12 dB, t_max = 10, the swept alpha, tau spectral, default grid.
+    Decisions are checked against the oracle on 300 sampled vectors of each
+    class; the padding of every row is zero."""
+    import torch
+    alpha = _alpha_star("mixed")
+    V = 100000
+    d = sim.gen_mixed(V, 12.0, sim.seed_for(3, snr_index=6))
+    desc = gpu_lib.make_desc(V, 1, 1, 2, prec=prec, t_max=10, alpha=alpha)
+    res = gpu_lib.run_mixed(desc, *_inputs(d), want_margin=False)
+    torch.cuda.synchronize()
+    sb, st = res["sbar"].cpu().numpy(), res["status"].cpu().numpy()
+    assert np.all(st == 0)
+    nm1 = np.where(d["mod"] == 2, 2 * d["U"], d["U"])
+    assert np.all(sb[np.arange(64)[None, :] >= nm1[:, None]] == 0)
+    mtol = {0: 1e-4, 1: 10 * 2.0 ** -8}[prec]
+    rng = np.random.default_rng(11)
+    for c in range(len(sim.MIXED_CLASSES)):
+        idx = np.sort(rng.choice(np.nonzero(d["cls"] == c)[0], size=300, replace=False))
+        B, U, mod = int(d["B"][idx[0]]), int(d["U"][idx[0]]), int(d["mod"][idx[0]])
+        H = np.stack([d["H_flat"][d["H_off"][v]:d["H_off"][v] + B * U].reshape(B, U) for v in idx])
+        y = np.stack([d["y_flat"][d["y_off"][v]:d["y_off"][v] + B] for v in idx])
+        ref = oracle.detect_coherent(H, y, mod, alpha=alpha, t_max=10)
+        n = oracle.problem_size(U, mod) - 1
+        assert_decisions(sb[idx, :n], ref["sbar"], ref["margin"], tol=mtol)

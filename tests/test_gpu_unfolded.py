@@ -188,3 +188,39 @@ def test_fp32_layouts_forward_and_gradient(gpu_lib, unf, B, U, mod, V, literal):
     assert np.max(rel_frobenius(L, L_ref)) <= L_REL_TOL
     assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
     assert np.max(np.abs(g - g_ref)) <= 1e-3 * np.max(np.abs(g_ref)), (g, g_ref)
+
+
+def test_training_batch_full_size(gpu_lib, unf):
+    """The training configuration: 16,384 vectors of 64x16 QPSK with SNR
+    U[4, 16] dB, t_max = 20.  The forward is checked against the oracle on
+    256 sampled vectors; the batch gradient, which no sample can check, by a
+    property that holds at any size: the gradient of the mean loss over the
+    batch is the size-weighted mean of the gradients over two halves."""
+    import torch
+    d = sim.gen_training_batch(64, 16, oracle.QPSK, 16384, 4.0, 16.0, sim.seed_for(4, 7, 0))
+    T = oracle.build_T_coherent(d["H"], d["y"], oracle.QPSK)
+    D, Tt, _ = oracle.precondition(T)
+    lam = oracle.spectral_norm(Tt)
+    s = d["s"]
+    sbar = np.concatenate([s.real, s.imag], axis=-1)
+    alpha = np.linspace(0.3, 1.0, 20)
+    Tt_, D_, lam_, s_ = to_dev(torch.float32, Tt, D, lam, sbar)
+    a = torch.tensor(alpha, dtype=torch.float32, device="cuda", requires_grad=True)
+    L = unf.unfolded(a, Tt_, D_, lam_)
+    unf.mse_loss(L, D_, s_).backward()
+    g_full = a.grad.clone()
+    idx = np.sort(np.random.default_rng(5).choice(16384, size=256, replace=False))
+    import torch as _t
+    Lref = oracle_unfolded(*(_t.from_numpy(np.asarray(x, dtype=np.float64)) for x in (Tt[idx], D[idx], lam[idx])),
+                           _t.tensor(alpha, dtype=_t.float64))
+    got = unpack_lower(L.detach().cpu().numpy()[idx].astype(np.float64), 33)
+    assert np.max(rel_frobenius(got, Lref.numpy())) <= L_REL_TOL
+    halves = []
+    for sl in (slice(0, 10000), slice(10000, 16384)):
+        a2 = torch.tensor(alpha, dtype=torch.float32, device="cuda", requires_grad=True)
+        L2 = unf.unfolded(a2, Tt_[sl].contiguous(), D_[sl].contiguous(), lam_[sl].contiguous())
+        unf.mse_loss(L2, D_[sl], s_[sl]).backward()
+        halves.append(a2.grad.clone())
+    combo = (10000 * halves[0] + 6384 * halves[1]) / 16384
+    torch.cuda.synchronize()
+    assert torch.allclose(g_full, combo, rtol=1e-4, atol=1e-6 * float(g_full.abs().max())), (g_full, combo)
