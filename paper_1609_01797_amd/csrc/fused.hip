@@ -163,8 +163,9 @@ constexpr int kPrepWaves = 4;
 
 // Preprocessing of one channel group (one wave): T~ in bordered form and the
 // step size, stored to the workspace in the register layout of the solve.
-// The complex Gram G = H^H H, b = H^H y and ||y||^2 arrive as MFMA
-// accumulators (lane (n, g) holds rows 4 g + r of column n).
+// The complex Gram arrives as MFMA accumulators (lane (n, g) holds rows
+// 4 g + r of column n): reG = Re G, imG = P = Hr^T Hi (Im G = P - P^T),
+// reb / imb = Re / Im of b = H^H y, and the lane's part of ||y||^2.
 __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, const f4& reG,
                                             const f4& imG, const f4& reb, const f4& imb,
                                             float ysq) {
@@ -182,14 +183,22 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
   float* yy2 = yy2_all[threadIdx.x >> 6];
 
   ysq = sum_groups(ysq);
+  // imG holds P = Hr^T Hi; Im G = P - P^T
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     Gs[(4 * g + r) * 16 + n] = make_float2(reG[r], imG[r]);
     bs[(4 * g + r) * 16 + n] = make_float2(reb[r], imb[r]);
   }
   if (g == 0) yy2[n] = ysq;
-  // one wave: its LDS accesses complete in program order; the barrier keeps
-  // the compiler from moving the reads below above the writes
+  // one wave: its LDS accesses complete in program order; the barriers keep
+  // the compiler from moving LDS reads and writes across each other
+  __builtin_amdgcn_wave_barrier();
+  float pt[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) pt[r] = Gs[n * 16 + 4 * g + r].y;
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Gs[(4 * g + r) * 16 + n].y = imG[r] - pt[r];
   __builtin_amdgcn_wave_barrier();
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
@@ -368,17 +377,19 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
 
 
 // One row-quad of the channel group: lane (n, g) holds H[4 q + g][n] and
-// y_n[4 q + g]; eight 16x16x4 MFMAs add its share of G and b.
-__device__ __forceinline__ void gram_rowquad(float2 h, float2 y, f4& reG, f4& imG, f4& reb,
-                                             f4& imb, float& ysq) {
+// y_n[4 q + g]; seven 16x16x4 MFMAs add its share of G and b.  Im G is not
+// accumulated directly: with P = Hr^T Hi, Im G = P - P^T (formed once the
+// sums are complete), and Im b = Hr^T yi - Hi^T yr comes from two
+// accumulators, so no operand needs a negated copy.
+__device__ __forceinline__ void gram_rowquad(float2 h, float2 y, f4& reG, f4& pG, f4& reb,
+                                             f4& ib1, f4& ib2, float& ysq) {
   reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
   reG = mfma(h.y, h.y, reG);
-  imG = mfma(h.x, h.y, imG);       // Im G = Hr^T Hi - Hi^T Hr
-  imG = mfma(h.y, -h.x, imG);
+  pG = mfma(h.x, h.y, pG);         // P = Hr^T Hi
   reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
   reb = mfma(h.y, y.y, reb);
-  imb = mfma(h.x, y.y, imb);       // Im b = Hr^T yi - Hi^T yr
-  imb = mfma(h.y, -y.x, imb);
+  ib1 = mfma(h.x, y.y, ib1);       // Hr^T yi
+  ib2 = mfma(h.y, y.x, ib2);       // Hi^T yr
   ysq += y.x * y.x + y.y * y.y;
 }
 
@@ -393,27 +404,41 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
   const int B = a.B;
   const float2* Hg = a.H + (grp * 16 / a.y_per_H) * (long long)B * 16;
   const float2* yv = a.y + (grp * 16 + n) * B;
-  f4 reG = {0.f, 0.f, 0.f, 0.f}, imG = reG, reb = reG, imb = reG;
+  f4 reG = {0.f, 0.f, 0.f, 0.f}, pG = reG, reb = reG, ib1 = reG, ib2 = reG;
   float ysq = 0.f;
   constexpr int kQ = 8;
-  float2 hc[kQ], yc[kQ], hnx[kQ], ynx[kQ];
+  float2 h0[kQ], y0[kQ], h1[kQ], y1[kQ];
+  // rows r0 + 4 q + g of the batch; whole batches (the common case) load
+  // without per-row guards, from one base pointer with immediate offsets
   auto load_batch = [&](int r0, float2 (&hb)[kQ], float2 (&yb)[kQ]) {
+    const float2* hp = Hg + (long long)(r0 + g) * 16 + n;
+    const float2* yp = yv + r0 + g;
+    if (r0 + 4 * kQ <= B) {
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const int row = r0 + 4 * q + g;
-      hb[q] = row < B ? Hg[(long long)row * 16 + n] : make_float2(0.f, 0.f);
-      yb[q] = row < B ? yv[row] : make_float2(0.f, 0.f);
+      for (int q = 0; q < kQ; ++q) { hb[q] = hp[64 * q]; yb[q] = yp[4 * q]; }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const bool in = r0 + 4 * q + g < B;
+        hb[q] = in ? hp[64 * q] : make_float2(0.f, 0.f);
+        yb[q] = in ? yp[4 * q] : make_float2(0.f, 0.f);
+      }
     }
   };
-  load_batch(0, hc, yc);
-  for (int r0 = 0; r0 < B; r0 += 4 * kQ) {
-    if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, hnx, ynx);
+  // two batches per trip, alternating buffers, so that no registers are
+  // copied between batches
+  load_batch(0, h0, y0);
+  for (int r0 = 0; r0 < B; r0 += 8 * kQ) {
+    if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, h1, y1);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) gram_rowquad(hc[q], yc[q], reG, imG, reb, imb, ysq);
+    for (int q = 0; q < kQ; ++q) gram_rowquad(h0[q], y0[q], reG, pG, reb, ib1, ib2, ysq);
+    if (r0 + 4 * kQ >= B) break;
+    if (r0 + 8 * kQ < B) load_batch(r0 + 8 * kQ, h0, y0);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) { hc[q] = hnx[q]; yc[q] = ynx[q]; }
+    for (int q = 0; q < kQ; ++q) gram_rowquad(h1[q], y1[q], reG, pG, reb, ib1, ib2, ysq);
   }
-  prep_finish(a, grp, reG, imG, reb, imb, ysq);
+  const f4 imb = ib1 - ib2;
+  prep_finish(a, grp, reG, pG, reb, imb, ysq);
 }
 
 
