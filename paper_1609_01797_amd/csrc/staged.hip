@@ -14,9 +14,23 @@ constexpr int kLanczosMax = 24;      // Krylov dimension cap for ||T~||_2
 constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
 
+// Sum over the 64 lanes of a wave, on the vector ALUs: rotations inside each
+// 16-lane row (DPP row_ror 8, 4, 2, 1), then the gfx950 lane swaps across
+// rows (permlane32 / permlane16: with both operands equal the two results
+// are a value and its partner's).  A shuffle-based reduction goes through
+// the LDS pipe, and the Lanczos reorthogonalisation makes hundreds of these
+// reductions one after another.
 __device__ inline float wave_sum(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xF, 0xF, false));
+  const unsigned u = __float_as_uint(v);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  v = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const unsigned w = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Sturm count: number of eigenvalues of the symmetric tridiagonal
@@ -194,8 +208,19 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
         const int r = lane + s * kWave;
         float acc = 0.f;
         if (r < N) {
+          // four independent partial sums so that the LDS loads of the row
+          // and of q pipeline instead of waiting one FMA at a time
           const float* row = T + (size_t)r * N;
-          for (int k = 0; k < N; ++k) acc += row[k] * q[k];
+          float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+          int k = 0;
+          for (; k + 4 <= N; k += 4) {
+            p0 += row[k] * q[k];
+            p1 += row[k + 1] * q[k + 1];
+            p2 += row[k + 2] * q[k + 2];
+            p3 += row[k + 3] * q[k + 3];
+          }
+          for (; k < N; ++k) p0 += row[k] * q[k];
+          acc = (p0 + p1) + (p2 + p3);
           dot += acc * q[r];
         }
         w[s] = acc;
