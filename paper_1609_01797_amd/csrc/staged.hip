@@ -95,11 +95,14 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   const bool qpsk = a.mod == TASER_QPSK;
 
   // LDS: [channel copy | Lanczos basis] (shared region), then T and D.
-  const size_t hbytes = (size_t)B * (U + 1) * sizeof(float2);
+  // channel columns padded to B + 1 entries: the threads of a wave read
+  // different columns at the same row, which would otherwise share a bank
+  const int BP = B + 1;
+  const size_t hbytes = (size_t)BP * (U + 1) * sizeof(float2);
   const size_t qbytes = (size_t)kLanczosMax * N * sizeof(float);
   const size_t region0 = hbytes > qbytes ? hbytes : qbytes;
-  float2* Hc = reinterpret_cast<float2*>(smem);        // [U][B] column-major channel
-  float2* yc = Hc + (size_t)U * B;                      // [B]
+  float2* Hc = reinterpret_cast<float2*>(smem);        // [U][BP] column-major channel
+  float2* yc = Hc + (size_t)U * BP;                     // [B]
   float* T = reinterpret_cast<float*>(reinterpret_cast<char*>(smem) + region0);  // [N][N]
   float* Dl = T + (size_t)N * N;                        // [N]
   __shared__ int flag_nonfinite, flag_degenerate;
@@ -109,14 +112,17 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
     const float2* Hg = a.H + (size_t)(v / a.y_per_H) * B * U;
     for (int e = tid; e < B * U; e += kBuildThreads) {
       const int b = e / U, u = e - b * U;
-      Hc[(size_t)u * B + b] = Hg[e];
+      Hc[(size_t)u * BP + b] = Hg[e];
     }
     const float2* yg = a.y + (size_t)v * B;
     for (int b = tid; b < B; b += kBuildThreads) yc[b] = yg[b];
   } else {
     const float2* Yg = a.y + (size_t)v * (U + 1) * B;
     const float2 s0 = a.s0[v];
-    for (int e = tid; e < U * B; e += kBuildThreads) Hc[e] = Yg[B + e];   // slots 1..K
+    for (int e = tid; e < U * B; e += kBuildThreads) {   // slots 1..K
+      const int u = e / B, b = e - u * B;
+      Hc[(size_t)u * BP + b] = Yg[B + e];
+    }
     for (int b = tid; b < B; b += kBuildThreads) {
       const float2 y0 = Yg[b];
       yc[b] = make_float2(y0.x * s0.x - y0.y * s0.y, y0.x * s0.y + y0.y * s0.x);
@@ -135,8 +141,8 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
       while (p * (p + 1) / 2 > e) --p;
       while ((p + 1) * (p + 2) / 2 <= e) ++p;
       const int q = e - p * (p + 1) / 2;
-      const float2* hp = Hc + (size_t)p * B;
-      const float2* hq = Hc + (size_t)q * B;
+      const float2* hp = Hc + (size_t)p * BP;
+      const float2* hq = Hc + (size_t)q * BP;
       for (int b = 0; b < B; ++b) {          // conj(h_p) h_q
         re += hp[b].x * hq[b].x + hp[b].y * hq[b].y;
         im += hp[b].x * hq[b].y - hp[b].y * hq[b].x;
@@ -152,7 +158,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
       }
     } else if (e < n_pairs + U) {
       const int p = e - n_pairs;
-      const float2* hp = Hc + (size_t)p * B;
+      const float2* hp = Hc + (size_t)p * BP;
       for (int b = 0; b < B; ++b) {          // conj(h_p) y
         re += hp[b].x * yc[b].x + hp[b].y * yc[b].y;
         im += hp[b].x * yc[b].y - hp[b].y * yc[b].x;
@@ -372,7 +378,7 @@ __global__ void detect_kernel(int32_t V, int32_t N, const float* __restrict__ L,
 }  // namespace
 
 size_t build_T_lds_bytes(int B, int U, int N) {
-  const size_t hbytes = (size_t)B * (U + 1) * sizeof(float2);
+  const size_t hbytes = (size_t)(B + 1) * (U + 1) * sizeof(float2);
   if (hbytes > (size_t)kLdsHBudget) return 0;
   size_t q = (size_t)kLanczosMax * N * sizeof(float);
   size_t first = hbytes > q ? hbytes : q;
