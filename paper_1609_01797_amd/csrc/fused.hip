@@ -60,7 +60,11 @@ __device__ __forceinline__ int or_groups(int x) {
   return (int)(r[0] | r[1]);
 }
 
+// Hardware reciprocal, square root and reciprocal square root (about one
+// ulp; the correctly rounded library forms cost some twenty instructions).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // 16-bit operands for the BF16 / FP16 products: four values packed in two
 // dwords, element e holding MFMA K position 4 (lane / 16) + e.
@@ -117,7 +121,7 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
   float x = -3.4e38f;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const float rad = (k > 0 ? sqrtf(b2[k - 1]) : 0.f) + (k < M - 1 ? sqrtf(b2[k]) : 0.f);
+    const float rad = (k > 0 ? hsqrt(b2[k - 1]) : 0.f) + (k < M - 1 ? hsqrt(b2[k]) : 0.f);
     x = fmaxf(x, al[k] + rad);
   }
   x = x * (1.f + 1e-6f) + 1e-30f;
@@ -138,7 +142,7 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
       Hs += r * r - f * id;
     }
     const float disc = fmaxf(0.f, (float)(M - 1) * ((float)M * Hs - G * G));
-    const float step = (float)M * rcp(G + sqrtf(disc));
+    const float step = (float)M * rcp(G + hsqrt(disc));
     if (!(step > 0.f) || !isfinite(step)) break;
     x -= step;
     // cubic convergence: once a step is this small the next one would be
@@ -205,14 +209,27 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
   bool bad_group = false, deg_group = false, bad_vec = false, deg_vec = false;
   auto Du = [&](int u) {
     const float d = fabsf(Gs[u * 17].x);
-    return d == 0.f ? 1.f : sqrtf(d);
+    return d == 0.f ? 1.f : hsqrt(d);
   };
   const float yn = yy2[n];
   deg_vec = yn == 0.f;
   bad_vec = !isfinite(yn);
-  const float DN = (yn == 0.f || !isfinite(yn)) ? 1.f : sqrtf(yn);
+  const float DN = (yn == 0.f || !isfinite(yn)) ? 1.f : hsqrt(yn);
 
-  // A operands: A[mt][kt][s] = G~[16 mt + jj(n)][16 kt + 4 s + g]
+  // per-lane column data: columns j = 16 mt + 4 r + g, user u = 4 r + g
+  float Dc[4], ct[2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int u = 4 * r + g;
+    Dc[r] = Du(u);
+    const float2 bu = bs[u * 16 + n];
+    if (!isfinite(bu.x) || !isfinite(bu.y)) bad_vec = true;
+    const float inv = rcp(Dc[r] * DN);
+    ct[0][r] = -bu.x * inv;          // last column of T: -Hbar^T ybar
+    ct[1][r] = -bu.y * inv;
+  }
+  // A operands: A[mt][kt][s] = G~[16 mt + jj(n)][16 kt + 4 s + g]; the
+  // column user 4 s + g is the lane's user of Dc[s]
   float A[2][2][4];
   {
     const int aa = 4 * (n & 3) + (n >> 2);
@@ -223,24 +240,12 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
       const int bb = 4 * s + g;
       const float2 gab = Gs[aa * 16 + bb];
       if (!isfinite(gab.x) || !isfinite(gab.y)) bad_group = true;
-      const float inv = 1.f / (da * Du(bb));
+      const float inv = rcp(da * Dc[s]);
       A[0][0][s] = gab.x * inv;
       A[0][1][s] = -gab.y * inv;
       A[1][0][s] = gab.y * inv;
       A[1][1][s] = gab.x * inv;
     }
-  }
-  // per-lane column data: columns j = 16 mt + 4 r + g, user u = 4 r + g
-  float Dc[4], ct[2][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int u = 4 * r + g;
-    Dc[r] = Du(u);
-    const float2 bu = bs[u * 16 + n];
-    if (!isfinite(bu.x) || !isfinite(bu.y)) bad_vec = true;
-    const float inv = 1.f / (Dc[r] * DN);
-    ct[0][r] = -bu.x * inv;          // last column of T: -Hbar^T ybar
-    ct[1][r] = -bu.y * inv;
   }
   // group-wide and per-vector flags
   const unsigned long long mg = __ballot(bad_group) | 0ull;
@@ -283,7 +288,7 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
 #pragma unroll
       for (int r = 0; r < 4; ++r) { Q[mt][r] = ct[mt][r]; Qp[mt][r] = 0.f; nrm += Q[mt][r] * Q[mt][r]; }
     nrm = sum_groups(nrm) + 1.f;
-    const float inv0 = 1.f / sqrtf(nrm);
+    const float inv0 = rsq(nrm);
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -326,10 +331,10 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          W[mt][r] -= alj * Q[mt][r] + beta * Qp[mt][r];
+          W[mt][r] = fmaf(-alj, Q[mt][r], fmaf(-beta, Qp[mt][r], W[mt][r]));
           ww += W[mt][r] * W[mt][r];
         }
-      w32 -= alj * q32 + beta * qp32;
+      w32 = fmaf(-alj, q32, fmaf(-beta, qp32, w32));
       const float bb = sum_groups(ww) + w32 * w32;
       // After a breakdown (an invariant Krylov subspace) the remaining
       // diagonal entries are parked far below the spectrum and decoupled.
@@ -342,8 +347,8 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
         al[j] = -1e30f;
         b2[j] = 0.f;
       }
-      beta = sqrtf(bb);
-      const float ib = beta > 0.f ? rcp(beta) : 0.f;
+      const float ib = bb > 0.f ? rsq(bb) : 0.f;
+      beta = bb * ib;                 // sqrt(bb)
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -474,6 +479,13 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
   const bool nonfinite = (fl & 2) != 0;
   const bool skip = fl != 0;
   const float m2tau = -2.f * tau;
+  // The register of row i that holds the diagonal (columns 4 (i / 4) + g)
+  // has lanes above the diagonal, g > i % 4.  There L~ is zero, so a zero
+  // step factor keeps V zero without a select: mdiag[d] is the factor for
+  // rows with i % 4 == d.
+  float mdiag[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) mdiag[d] = g <= d ? m2tau : 0.f;
   constexpr bool k16 = P != TASER_PREC_F32;
   u2 Ah[2][2];
   if constexpr (k16) {
@@ -595,10 +607,9 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
         sfor<0, 4>([&](auto rc) {
           constexpr int R = decltype(rc)::value;
           if constexpr (16 * MT + 4 * R <= I) {
-            float x = fmaf(m2tau, ring[SLOT][MT][R], Lr[I][MT][R]);
-            if constexpr (16 * MT + 4 * R + 3 > I) {
-              if (g > I - 16 * MT - 4 * R) x = 0.f;   // strictly upper part
-            }
+            float m = m2tau;
+            if constexpr (16 * MT + 4 * R + 3 > I) m = mdiag[I - 16 * MT - 4 * R];
+            const float x = fmaf(m, ring[SLOT][MT][R], Lr[I][MT][R]);
             Lr[I][MT][R] = x;
             nsq[MT][R] = fmaf(x, x, nsq[MT][R]);
           }
