@@ -92,7 +92,11 @@ __device__ __forceinline__ int or_all(int x) {
   return __ballot(x != 0) != 0ull;
 }
 
+// Hardware reciprocal, square root and reciprocal square root (about one
+// ulp; the correctly rounded library forms cost some twenty instructions).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 constexpr int kLanczos = 12;
 
@@ -108,7 +112,7 @@ __device__ __forceinline__ float top_eigenvalue(const float (&al)[M], const floa
   float lo = -3.4e38f, hi = -3.4e38f;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const float rad = (k > 0 ? sqrtf(b2[k - 1]) : 0.f) + (k < M - 1 ? sqrtf(b2[k]) : 0.f);
+    const float rad = (k > 0 ? hsqrt(b2[k - 1]) : 0.f) + (k < M - 1 ? hsqrt(b2[k]) : 0.f);
     hi = fmaxf(hi, al[k] + rad);
     lo = fmaxf(lo, al[k]);
   }
@@ -304,26 +308,27 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     const bool real_k = k < Nm1 || k == N1;
     const float d = nonfinite ? 0.f : fabsf(T[k * LD + k]);
     if (real_k && d == 0.f) deg = 1;
-    Dl[k] = (d == 0.f || !real_k) ? 1.f : sqrtf(d);
+    Dl[k] = (d == 0.f || !real_k) ? 1.f : hsqrt(d);
   }
   const bool degenerate = !nonfinite && or_all(deg);
   const bool skip = nonfinite || degenerate;
   __syncthreads();
   const float DN = Dl[N1];
-  const float tNN = skip ? 0.f : T[N1 * LD + N1] / (DN * DN);
+  const float iDN = rcp(DN);
+  const float tNN = skip ? 0.f : T[N1 * LD + N1] * (iDN * iDN);
   float A[NT][NT][4];
   {
     const int jr = 4 * (n & 3) + (n >> 2);
     sfor<0, NT>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
       const int j = 16 * JT + jr;
-      const float dj = Dl[j];
+      const float idj = rcp(Dl[j]);
       sfor<0, NT>([&](auto kc) {
         constexpr int KT = decltype(kc)::value;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = 16 * KT + 4 * s + g;
-          A[JT][KT][s] = skip ? 0.f : T[j * LD + k] / (dj * Dl[k]);
+          A[JT][KT][s] = skip ? 0.f : T[j * LD + k] * (idj * rcp(Dl[k]));
         }
       });
     });
@@ -337,7 +342,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       const int j = 16 * JT + 4 * r + g;
       act[JT][r] = j < Nm1;
       Dc[JT][r] = Dl[j];
-      ct[JT][r] = skip ? 0.f : T[j * LD + N1] / (Dl[j] * DN);
+      ct[JT][r] = skip ? 0.f : T[j * LD + N1] * (rcp(Dl[j]) * iDN);
     }
   });
   __syncthreads();   // T is dead from here on; sh may be reused freely
@@ -414,9 +419,10 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Wv[JT][r] -= alj * Q[JT][r] + beta * Qp[JT][r];
+        for (int r = 0; r < 4; ++r)
+          Wv[JT][r] = fmaf(-alj, Q[JT][r], fmaf(-beta, Qp[JT][r], Wv[JT][r]));
       });
-      w32 -= alj * q32 + beta * qp32;
+      w32 = fmaf(-alj, q32, fmaf(-beta, qp32, w32));
       const float bb = dot(Wv, Wv) + w32 * w32;
       if (!done) {
         al[J] = alj;
@@ -427,8 +433,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
         al[J] = -1e30f;
         b2[J] = 0.f;
       }
-      beta = sqrtf(bb);
-      const float ib = beta > 0.f ? rcp(beta) : 0.f;
+      const float ib = bb > 0.f ? rsq(bb) : 0.f;
+      beta = bb * ib;                 // sqrt(bb)
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;
 #pragma unroll

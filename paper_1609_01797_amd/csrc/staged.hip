@@ -33,6 +33,12 @@ __device__ inline float wave_sum(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// Hardware reciprocal, square root and reciprocal square root (about one
+// ulp; the correctly rounded library forms cost some twenty instructions).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Sturm count: number of eigenvalues of the symmetric tridiagonal
 // (a[0..m-1], b[0..m-2]) that are smaller than x.
 __device__ int sturm_count(const float* a, const float* b2, int m, float x, float pivmin) {
@@ -41,7 +47,7 @@ __device__ int sturm_count(const float* a, const float* b2, int m, float x, floa
   if (fabsf(d) < pivmin) d = -pivmin;
   cnt += d < 0.f;
   for (int i = 1; i < m; ++i) {
-    d = a[i] - x - b2[i - 1] / d;
+    d = a[i] - x - b2[i - 1] * rcp(d);
     if (fabsf(d) < pivmin) d = -pivmin;
     cnt += d < 0.f;
   }
@@ -54,7 +60,7 @@ __device__ float tridiag_extreme(const float* a, const float* b2, int m, float l
                                  bool want_max, float pivmin) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int round = 0; round < 6; ++round) {
-    const float w = (hi - lo) / 65.f;
+    const float w = (hi - lo) * (1.f / 65.f);
     const float x = lo + w * (float)(lane + 1);
     const int c = sturm_count(a, b2, m, x, pivmin);
     // want_max: first point with every eigenvalue below it bounds lambda_max
@@ -180,13 +186,13 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   for (int k = tid; k < N; k += kBuildThreads) {
     const float d = nonfinite ? 0.f : fabsf(T[k * N + k]);
     if (d == 0.f) flag_degenerate = 1;
-    Dl[k] = d == 0.f ? 1.f : sqrtf(d);
+    Dl[k] = d == 0.f ? 1.f : hsqrt(d);
   }
   __syncthreads();
   float* Ttg = a.Tt + (size_t)v * N * N;
   for (int e = tid; e < N * N; e += kBuildThreads) {
     const int i = e / N, j = e - i * N;
-    const float t = nonfinite ? 0.f : T[e] / (Dl[i] * Dl[j]);
+    const float t = nonfinite ? 0.f : T[e] * rcp(Dl[i] * Dl[j]);
     T[e] = t;
     Ttg[e] = t;
   }
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
     float nrm = 0.f;
     for (int r = lane; r < N; r += kWave) { const float s = start_entry(r); nrm += s * s; }
     nrm = wave_sum(nrm);
-    const float inv0 = 1.f / sqrtf(nrm);
+    const float inv0 = rsq(nrm);
     for (int r = lane; r < N; r += kWave) Q[r] = start_entry(r) * inv0;
     int m = 0;
     float scale = 0.f;
@@ -249,12 +255,12 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
       float bb = 0.f;
       for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) bb += w[s] * w[s]; }
       bb = wave_sum(bb);
-      const float beta = sqrtf(bb);
+      const float ib = bb > 0.f ? rsq(bb) : 0.f;
+      const float beta = bb * ib;          // sqrt(bb)
       scale = fmaxf(scale, beta);
       if (!(beta > 1e-6f * scale)) break;   // invariant subspace found
       if (lane == 0) be2[j] = bb;
       float* qn = Q + (size_t)(j + 1) * N;
-      const float ib = 1.f / beta;
       for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) qn[r] = w[s] * ib; }
       __builtin_amdgcn_wave_barrier();
     }
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
     // Gershgorin interval of the Ritz tridiagonal
     float lo = 3.4e38f, hi = -3.4e38f;
     for (int i = 0; i < m; ++i) {
-      const float r = (i > 0 ? sqrtf(be2[i - 1]) : 0.f) + (i < m - 1 ? sqrtf(be2[i]) : 0.f);
+      const float r = (i > 0 ? hsqrt(be2[i - 1]) : 0.f) + (i < m - 1 ? hsqrt(be2[i]) : 0.f);
       lo = fminf(lo, al[i] - r);
       hi = fmaxf(hi, al[i] + r);
     }
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(192) void solve_kernel(int N, int t_max, int flags,
         float nsq = 0.f;
         for (int i = j; i < N; ++i) { const float x = Vp[tri(i, j)]; nsq += x * x; }
         if (nsq > 0.f && isfinite(nsq)) {
-          const float s = Dj / sqrtf(nsq);
+          const float s = Dj * rsq(nsq);
           for (int i = j; i < N; ++i) Lp[tri(i, j)] = Vp[tri(i, j)] * s;
         } else {
           Lp[tri(j, j)] = Dj;

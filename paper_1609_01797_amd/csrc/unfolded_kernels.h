@@ -84,7 +84,7 @@ __device__ __forceinline__ void load4(const Real* p, Real (&r)[4]) {
 template <typename Real>
 __device__ __forceinline__ Real inv_sqrt(Real x) {
   if constexpr (sizeof(Real) == 8) return 1.0 / sqrt(x);
-  else return 1.f / sqrtf(x);
+  else return __builtin_amdgcn_rsqf(x);   // hardware rsqrt, about one ulp
 }
 
 // Sum over the CW lanes of one vector.
