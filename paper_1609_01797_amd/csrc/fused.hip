@@ -152,11 +152,14 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
   return x;
 }
 
-// Workspace per channel group (floats): the MFMA A operands of G~, the border
-// c~, the column scales D and per-lane D_NN, tau and flags, stored
-// register-major ([register][lane]) so both kernels move them coalesced.
-constexpr int kWsA = 0, kWsC = 1024, kWsD = 1536, kWsDN = 1792, kWsTau = 1856, kWsFlag = 1920;
-constexpr int kWsFloats = 2048;
+// Workspace per channel group (floats): the MFMA A operands of G~ (its real
+// and imaginary parts R and M; the real form [[R, -M], [M, R]] is rebuilt in
+// registers), the border c~, the column scales D and per-lane D_NN, tau and
+// flags, stored register-major ([register][lane]) so both kernels move them
+// coalesced.
+constexpr int kWsR = 0, kWsM = 256, kWsC = 512, kWsD = 1024, kWsDN = 1280, kWsTau = 1344,
+              kWsFlag = 1408;
+constexpr int kWsFloats = 1472;
 
 // Waves (channel groups) per workgroup of the preparation kernel.  Its
 // waves need few registers, so five would fit on a SIMD; four-wave
@@ -296,29 +299,34 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
     q32 = inv0;
     bool done = false;
     float scale = 0.f;
+    // G~ = R + i M is Hermitian with real form [[R, -M], [M, R]] (the blocks
+    // A[0][0] and A[1][0]), so G~ q for q = [c; d] takes three real products
+    // instead of four (Gauss's complex product):
+    //   k1 = (R + M) c,  k2 = R (d - c),  k3 = M (c + d),
+    //   [R c - M d; M c + R d] = [k1 - k3; k1 + k2].
+    float Apm[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) Apm[s] = A[0][0][s] + A[1][0][s];
     sfor<0, kLanczosSteps>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      // four independent accumulation chains (mt, kt) keep the MFMA pipe full
-      f4 acc[2][2];
+      f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt) acc[mt][kt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-          for (int kt = 0; kt < 2; ++kt) acc[mt][kt] = mfma(A[mt][kt][s], Q[kt][s], acc[mt][kt]);
+      for (int s = 0; s < 4; ++s) {
+        k1 = mfma(Apm[s], Q[0][s], k1);
+        k2 = mfma(A[0][0][s], Q[1][s] - Q[0][s], k2);
+        k3 = mfma(A[1][0][s], Q[0][s] + Q[1][s], k3);
+      }
       float W[2][4];
       float cq = 0.f;
 #pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        W[0][r] = (k1[r] - k3[r]) + ct[0][r] * q32;
+        W[1][r] = (k1[r] + k2[r]) + ct[1][r] * q32;
+      }
+#pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          W[mt][r] = (acc[mt][0][r] + acc[mt][1][r]) + ct[mt][r] * q32;
-          cq += ct[mt][r] * Q[mt][r];
-        }
+        for (int r = 0; r < 4; ++r) cq += ct[mt][r] * Q[mt][r];
       float w32 = sum_groups(cq) + q32;
       float dot = 0.f;
 #pragma unroll
@@ -362,11 +370,10 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
   // ---------------- hand the group's state to the solve kernel ----------------
   float* ws = a.ws + grp * kWsFloats;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) ws[kWsA + ((mt * 2 + kt) * 4 + s) * 64 + lane] = A[mt][kt][s];
+  for (int s = 0; s < 4; ++s) {
+    ws[kWsR + s * 64 + lane] = A[0][0][s];
+    ws[kWsM + s * 64 + lane] = A[1][0][s];
+  }
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -382,19 +389,19 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
 
 
 // One row-quad of the channel group: lane (n, g) holds H[4 q + g][n] and
-// y_n[4 q + g]; seven 16x16x4 MFMAs add its share of G and b.  Im G is not
+// y_n[4 q + g]; six 16x16x4 MFMAs add its share of G and b.  Im G is not
 // accumulated directly: with P = Hr^T Hi, Im G = P - P^T (formed once the
-// sums are complete), and Im b = Hr^T yi - Hi^T yr comes from two
-// accumulators, so no operand needs a negated copy.
-__device__ __forceinline__ void gram_rowquad(float2 h, float2 y, f4& reG, f4& pG, f4& reb,
-                                             f4& ib1, f4& ib2, float& ysq) {
+// sums are complete).  b = H^H y takes three real products (Gauss's complex
+// product): k1 = (Hr - Hi)^T yr, k2 = Hr^T (yi - yr), k3 = Hi^T (yr + yi),
+// Re b = k1 + k3, Im b = k1 + k2.
+__device__ __forceinline__ void gram_rowquad(float2 h, float2 y, f4& reG, f4& pG, f4& k1,
+                                             f4& k2, f4& k3, float& ysq) {
   reG = mfma(h.x, h.x, reG);       // Re G = Hr^T Hr + Hi^T Hi
   reG = mfma(h.y, h.y, reG);
   pG = mfma(h.x, h.y, pG);         // P = Hr^T Hi
-  reb = mfma(h.x, y.x, reb);       // Re b = Hr^T yr + Hi^T yi
-  reb = mfma(h.y, y.y, reb);
-  ib1 = mfma(h.x, y.y, ib1);       // Hr^T yi
-  ib2 = mfma(h.y, y.x, ib2);       // Hi^T yr
+  k1 = mfma(h.x - h.y, y.x, k1);
+  k2 = mfma(h.x, y.y - y.x, k2);
+  k3 = mfma(h.y, y.x + y.y, k3);
   ysq += y.x * y.x + y.y * y.y;
 }
 
@@ -409,13 +416,30 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
   const int B = a.B;
   const float2* Hg = a.H + (grp * 16 / a.y_per_H) * (long long)B * 16;
   const float2* yv = a.y + (grp * 16 + n) * B;
-  f4 reG = {0.f, 0.f, 0.f, 0.f}, pG = reG, reb = reG, ib1 = reG, ib2 = reG;
+  f4 reG = {0.f, 0.f, 0.f, 0.f}, pG = reG, k1 = reG, k2 = reG, k3 = reG;
   float ysq = 0.f;
   constexpr int kQ = 8;
   float2 h0[kQ], y0[kQ], h1[kQ], y1[kQ];
-  // rows r0 + 4 q + g of the batch; whole batches (the common case) load
-  // without per-row guards, from one base pointer with immediate offsets
+  // Any assignment of a batch's rows to the (slot, lane) pairs gives the same
+  // sums as long as h and y agree.  Whole batches (the common case) load
+  // without per-row guards, from one base pointer with immediate offsets:
+  // with B even, slot 2 p + e holds row r0 + 8 p + 2 g + e, so each lane
+  // reads two consecutive entries of y in one 16-byte load; otherwise (and
+  // in the last, partial batch) slot q holds row r0 + 4 q + g.
   auto load_batch = [&](int r0, float2 (&hb)[kQ], float2 (&yb)[kQ]) {
+    if (r0 + 4 * kQ <= B && (B & 1) == 0) {
+      const float2* hp = Hg + (long long)(r0 + 2 * g) * 16 + n;
+      const float4* yp = reinterpret_cast<const float4*>(yv + r0 + 2 * g);
+#pragma unroll
+      for (int p = 0; p < kQ / 2; ++p) {
+        const float4 t = yp[4 * p];
+        yb[2 * p] = make_float2(t.x, t.y);
+        yb[2 * p + 1] = make_float2(t.z, t.w);
+        hb[2 * p] = hp[128 * p];
+        hb[2 * p + 1] = hp[128 * p + 16];
+      }
+      return;
+    }
     const float2* hp = Hg + (long long)(r0 + g) * 16 + n;
     const float2* yp = yv + r0 + g;
     if (r0 + 4 * kQ <= B) {
@@ -436,14 +460,13 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
   for (int r0 = 0; r0 < B; r0 += 8 * kQ) {
     if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, h1, y1);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) gram_rowquad(h0[q], y0[q], reG, pG, reb, ib1, ib2, ysq);
+    for (int q = 0; q < kQ; ++q) gram_rowquad(h0[q], y0[q], reG, pG, k1, k2, k3, ysq);
     if (r0 + 4 * kQ >= B) break;
     if (r0 + 8 * kQ < B) load_batch(r0 + 8 * kQ, h0, y0);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) gram_rowquad(h1[q], y1[q], reG, pG, reb, ib1, ib2, ysq);
+    for (int q = 0; q < kQ; ++q) gram_rowquad(h1[q], y1[q], reG, pG, k1, k2, k3, ysq);
   }
-  const f4 imb = ib1 - ib2;
-  prep_finish(a, grp, reG, pG, reb, imb, ysq);
+  prep_finish(a, grp, reG, pG, k1 + k3, k1 + k2, ysq);
 }
 
 
@@ -462,11 +485,13 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
   const float* ws = a.ws + (long long)blockIdx.x * kWsFloats;
   float A[2][2][4], ct[2][4], Dc[4];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) A[mt][kt][s] = ws[kWsA + ((mt * 2 + kt) * 4 + s) * 64 + lane];
+  for (int s = 0; s < 4; ++s) {
+    const float re = ws[kWsR + s * 64 + lane], im = ws[kWsM + s * 64 + lane];
+    A[0][0][s] = re;
+    A[0][1][s] = -im;
+    A[1][0][s] = im;
+    A[1][1][s] = re;
+  }
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll

@@ -96,7 +96,7 @@ def test_workspace_size_query():
     n = ctypes.c_size_t(0)
     d = taser.make_desc(65536, 128, 16, taser.QPSK, y_per_H=16)
     assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
-    assert n.value == 4096 * 2048 * 4
+    assert n.value == 4096 * 1472 * 4      # 1,472 floats of state per group of 16 vectors
     assert lib.taser_workspace_size(ctypes.byref(d), None) == taser.ERR_ARG
     other = taser.make_desc(64, 32, 8, taser.QPSK)      # per-vector kernel: no workspace
     assert lib.taser_workspace_size(ctypes.byref(other), ctypes.byref(n)) == taser.OK and n.value == 0
