@@ -172,10 +172,12 @@ constexpr int kPrepWaves = 4;
 // step size, stored to the workspace in the register layout of the solve.
 // The complex Gram arrives as MFMA accumulators (lane (n, g) holds rows
 // 4 g + r of column n): reG = Re G, imG = P = Hr^T Hi (Im G = P - P^T),
-// reb / imb = Re / Im of b = H^H y, and the lane's part of ||y||^2.
-__device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, const f4& reG,
-                                            const f4& imG, const f4& reb, const f4& imb,
-                                            float ysq) {
+// reb / imb = Re / Im of b = H^H y, and the lane's part of ||y||^2.  Every
+// wave of the workgroup calls it (the step size uses workgroup barriers);
+// waves without a group (active false) compute on zeros and store nothing.
+__device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, bool active,
+                                            const f4& reG, const f4& imG, const f4& reb,
+                                            const f4& imb, float ysq) {
   // one LDS region per wave of the workgroup (each wave is one group)
   __shared__ float2 Gs_all[kPrepWaves][16 * 16];   // G = H^H H, [row][col]
   __shared__ float2 bs_all[kPrepWaves][16 * 16];   // b = H^H y, [user][vector]
@@ -279,7 +281,7 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
   // ---------------- step size tau = alpha / ||T~||_2 ----------------
   float tau;
   if (a.tau_mode == TASER_TAU_GIVEN) {
-    tau = a.tau_in[v];
+    tau = active ? a.tau_in[v] : 1.f;
   } else {
     // Lanczos from T~ e_N = [c~; 1] (a good start: the dominant eigenvector of
     // T~ weighs the last coordinate heavily), plain three-term recurrence.
@@ -364,9 +366,36 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, c
       qp32 = q32;
       q32 = w32 * ib;
     });
-    const float lam = tridiag_top<kLanczosSteps>(al, b2);
+    // The top eigenvalue of each tridiagonal is a serial recurrence per
+    // vector, which the four lanes of a vector would repeat.  Instead one
+    // wave of the workgroup takes all 64 vectors of its four groups, one per
+    // lane (the wave chosen by the workgroup index, so that on a CU the work
+    // spreads over the SIMDs).
+    __shared__ float tri_all[kPrepWaves][2 * kLanczosSteps][16];   // al, then b2
+    __shared__ float lam_all[kPrepWaves][16];
+    const int w = threadIdx.x >> 6;
+    if (g == 0) {
+#pragma unroll
+      for (int k = 0; k < kLanczosSteps; ++k) {
+        tri_all[w][k][n] = al[k];
+        tri_all[w][kLanczosSteps + k][n] = b2[k];
+      }
+    }
+    __syncthreads();
+    if (w == (int)(blockIdx.x & (kPrepWaves - 1))) {
+      float al2[kLanczosSteps], b22[kLanczosSteps];
+#pragma unroll
+      for (int k = 0; k < kLanczosSteps; ++k) {
+        al2[k] = tri_all[lane >> 4][k][n];
+        b22[k] = tri_all[lane >> 4][kLanczosSteps + k][n];
+      }
+      lam_all[lane >> 4][n] = tridiag_top<kLanczosSteps>(al2, b22);
+    }
+    __syncthreads();
+    const float lam = lam_all[w][n];
     tau = a.alpha / (lam > 0.f ? lam : 1.f);
   }
+  if (!active) return;
   // ---------------- hand the group's state to the solve kernel ----------------
   float* ws = a.ws + grp * kWsFloats;
 #pragma unroll
@@ -412,8 +441,9 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
   const int n = lane & 15;
   const int g = lane >> 4;
   const long long grp = (long long)blockIdx.x * kPrepWaves + (threadIdx.x >> 6);
-  if (grp >= groups) return;     // whole waves only; no workgroup barrier follows
-  const int B = a.B;
+  // waves past the last group stay for the workgroup barriers of the step size
+  const bool active = grp < groups;
+  const int B = active ? a.B : 0;
   const float2* Hg = a.H + (grp * 16 / a.y_per_H) * (long long)B * 16;
   const float2* yv = a.y + (grp * 16 + n) * B;
   f4 reG = {0.f, 0.f, 0.f, 0.f}, pG = reG, k1 = reG, k2 = reG, k3 = reG;
@@ -466,7 +496,7 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
 #pragma unroll
     for (int q = 0; q < kQ; ++q) gram_rowquad(h1[q], y1[q], reG, pG, k1, k2, k3, ysq);
   }
-  prep_finish(a, grp, reG, pG, k1 + k3, k1 + k2, ysq);
+  prep_finish(a, grp, active, reG, pG, k1 + k3, k1 + k2, ysq);
 }
 
 
