@@ -179,6 +179,15 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
                                int32_t* status, float* L_out, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* The step size tau = alpha / ||T~||_2 (Section III-B) of every vector, as
+   taser_run_prep left it in `ws` (or the tau_in it was given), copied to
+   tau: float32 [V], device memory owned by the caller.  With the computed
+   tau a caller can rerun the same batch with TASER_TAU_GIVEN.  Same
+   descriptor and workspace rules as taser_run_solve; errors:
+   TASER_ERR_ARG (tau NULL), TASER_ERR_WORKSPACE, TASER_ERR_UNSUPPORTED. */
+taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws_bytes,
+                             float* tau, void* stream);
+
 /* ---- Mixed-size batches ------------------------------------------------
 
    Coherent detection of V vectors of different sizes in one call: vector v

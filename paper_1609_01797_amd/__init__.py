@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
            "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
 
@@ -99,6 +99,8 @@ def load():
     lib.taser_run_prep.argtypes = [D, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_solve.restype = ctypes.c_int
     lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.taser_run_tau.restype = ctypes.c_int
+    lib.taser_run_tau.argtypes = [D, _P, ctypes.c_size_t, _P, _P]
     U = ctypes.POINTER(UnfoldedDesc)
     lib.taser_unfolded_sizes.restype = ctypes.c_int
     lib.taser_unfolded_sizes.argtypes = [U, ctypes.POINTER(ctypes.c_size_t),
@@ -340,6 +342,18 @@ def run_solve(desc: Desc, out, want_margin=False, want_L=False, ws=None, device=
                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()), _stream(dev))
     _raise(st)
     return res
+
+
+def run_tau(desc: Desc, ws, device=None):
+    """Step sizes tau [V] (float32) of a workspace ``run_prep`` filled."""
+    torch = _torch()
+    lib = load()
+    dev = device if device is not None else ws.device
+    tau = torch.empty(desc.num_vectors, dtype=torch.float32, device=dev)
+    st = lib.taser_run_tau(ctypes.byref(desc), ctypes.c_void_p(ws.data_ptr()),
+                           ctypes.c_size_t(ws.numel()), ctypes.c_void_p(tau.data_ptr()), _stream(dev))
+    _raise(st)
+    return tau
 
 
 MIXED_STRIDE = 64

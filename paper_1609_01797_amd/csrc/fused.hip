@@ -104,9 +104,12 @@ __device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
 }
 
 // Krylov dimension for ||T~||_2.  Twelve steps of the plain float32
-// recurrence reach the float32 resolution of the top Ritz value on these
-// matrices; more steps start to produce ghost copies of it (loss of
-// orthogonality), which slows Laguerre's method down to linear convergence.
+// recurrence from [c~; 1] bring the top Ritz value within 1e-6 of ||T~||_2 on
+// 128x16 channels from 0 dB up; at -4 dB about one vector in 4,000 is still
+// 2e-5 below it (its top eigenvalue is less dominant).  One or two more steps
+// would close that but produce ghost copies of the converged Ritz value (loss
+// of orthogonality), which slow Laguerre's method to linear convergence and
+// cost more than the steps themselves.
 constexpr int kLanczosSteps = 12;
 constexpr int kLaguerreIters = 8;
 
@@ -285,7 +288,12 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
   } else {
     // Lanczos from T~ e_N = [c~; 1] (a good start: the dominant eigenvector of
     // T~ weighs the last coordinate heavily), plain three-term recurrence.
-    float al[kLanczosSteps], b2[kLanczosSteps];
+    // alpha_j and beta_j^2 go straight to LDS, where one wave of the
+    // workgroup takes them for the eigenvalue step below; a rolled loop
+    // keeps the kernel's code small.
+    __shared__ float tri_all[kPrepWaves][2 * kLanczosSteps][16];   // al, then b2
+    __shared__ float lam_all[kPrepWaves][16];
+    const int w = threadIdx.x >> 6;
     float Q[2][4], Qp[2][4], q32, qp32 = 0.f, beta = 0.f;
     float nrm = 0.f;
 #pragma unroll
@@ -309,8 +317,8 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
     float Apm[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) Apm[s] = A[0][0][s] + A[1][0][s];
-    sfor<0, kLanczosSteps>([&](auto jc) {
-      constexpr int j = decltype(jc)::value;
+#pragma unroll 2
+    for (int j = 0; j < kLanczosSteps; ++j) {
       f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -348,14 +356,16 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
       const float bb = sum_groups(ww) + w32 * w32;
       // After a breakdown (an invariant Krylov subspace) the remaining
       // diagonal entries are parked far below the spectrum and decoupled.
+      float alo = -1e30f, b2o = 0.f;
       if (!done) {
-        al[j] = alj;
-        b2[j] = bb;
+        alo = alj;
+        b2o = bb;
         scale = fmaxf(scale, fabsf(alj));
-        if (!(bb > 1e-12f * scale * scale)) { done = true; b2[j] = 0.f; }
-      } else {
-        al[j] = -1e30f;
-        b2[j] = 0.f;
+        if (!(bb > 1e-12f * scale * scale)) { done = true; b2o = 0.f; }
+      }
+      if (g == 0) {
+        tri_all[w][j][n] = alo;
+        tri_all[w][kLanczosSteps + j][n] = b2o;
       }
       const float ib = bb > 0.f ? rsq(bb) : 0.f;
       beta = bb * ib;                 // sqrt(bb)
@@ -365,22 +375,12 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
         for (int r = 0; r < 4; ++r) { Qp[mt][r] = Q[mt][r]; Q[mt][r] = W[mt][r] * ib; }
       qp32 = q32;
       q32 = w32 * ib;
-    });
+    }
     // The top eigenvalue of each tridiagonal is a serial recurrence per
     // vector, which the four lanes of a vector would repeat.  Instead one
     // wave of the workgroup takes all 64 vectors of its four groups, one per
     // lane (the wave chosen by the workgroup index, so that on a CU the work
     // spreads over the SIMDs).
-    __shared__ float tri_all[kPrepWaves][2 * kLanczosSteps][16];   // al, then b2
-    __shared__ float lam_all[kPrepWaves][16];
-    const int w = threadIdx.x >> 6;
-    if (g == 0) {
-#pragma unroll
-      for (int k = 0; k < kLanczosSteps; ++k) {
-        tri_all[w][k][n] = al[k];
-        tri_all[w][kLanczosSteps + k][n] = b2[k];
-      }
-    }
     __syncthreads();
     if (w == (int)(blockIdx.x & (kPrepWaves - 1))) {
       float al2[kLanczosSteps], b22[kLanczosSteps];
@@ -808,6 +808,19 @@ hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_F16>, dim3(groups), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(solve_group_qpsk16<TASER_PREC_F32>, dim3(groups), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// tau[v] of every vector from a prepared workspace (lane n of a group's tau
+// row holds vector n).
+__global__ __launch_bounds__(256) void read_tau(const float* __restrict__ ws, int V,
+                                                float* __restrict__ tau) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < V) tau[v] = ws[(long long)(v / 16) * kWsFloats + kWsTau + (v & 15)];
+}
+
+hipError_t launch_fused_tau(const FusedArgs& a, float* tau, hipStream_t s) {
+  hipLaunchKernelGGL(read_tau, dim3((a.V + 255) / 256), dim3(256), 0, s, a.ws, a.V, tau);
   return hipGetLastError();
 }
 

@@ -199,6 +199,22 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
                                                                               : TASER_ERR_DEVICE;
 }
 
+taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws_bytes,
+                             float* tau, void* stream) {
+  FusedArgs a;
+  taser_status_t st = fused_args(desc, &a);
+  if (st != TASER_OK) return st;
+  if (!fused_group_supported(a)) return TASER_ERR_UNSUPPORTED;
+  if (a.V == 0) return TASER_OK;
+  if (!tau) return TASER_ERR_ARG;
+  const size_t need = fused_workspace_bytes(a);
+  if (!ws || ws_bytes < need) return TASER_ERR_WORKSPACE;
+  a.ws = static_cast<float*>(const_cast<void*>(ws));
+  return launch_fused_tau(a, tau, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
 static taser_status_t mixed_check(const taser_desc_t* d) {
   if (!d) return TASER_ERR_ARG;
   if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)

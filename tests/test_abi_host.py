@@ -106,6 +106,11 @@ def test_workspace_size_query():
     z = ctypes.c_void_p(0)
     one = ctypes.c_void_p(16)   # non-null but never dereferenced: the call fails first
     assert lib.taser_run(ctypes.byref(d), one, one, z, z, one, z, one, z, z, 0, z) == taser.ERR_WORKSPACE
+    # step-size readout: tau pointer and workspace checked before any launch
+    assert lib.taser_run_tau(ctypes.byref(d), one, 4096 * 1472 * 4, z, z) == taser.ERR_ARG
+    assert lib.taser_run_tau(ctypes.byref(d), one, 16, one, z) == taser.ERR_WORKSPACE
+    assert lib.taser_run_tau(ctypes.byref(d), z, 4096 * 1472 * 4, one, z) == taser.ERR_WORKSPACE
+    assert lib.taser_run_tau(ctypes.byref(other), one, 1 << 20, one, z) == taser.ERR_UNSUPPORTED
 
 
 def test_binding_refuses_cpu_tensors():

@@ -208,3 +208,34 @@ def test_fused_prep_then_solve_equals_run(gpu_lib):
     out16 = gpu_lib.run_solve(desc16, {"status": out["status"].clone()}, want_L=True, ws=ws, device=H.device)
     torch.cuda.synchronize()
     assert torch.equal(out16["L"], ref16["L"]) and torch.equal(out16["sbar"], ref16["sbar"])
+
+
+@pytest.mark.parametrize("snr, below", [(-4.0, 3e-5), (0.0, 1e-5), (10.0, 1e-5), (30.0, 1e-5)])
+def test_fused_step_size_pin(gpu_lib, snr, below):
+    """The preparation's ||T~||_2 (12 Lanczos steps from [c~; 1] + Laguerre,
+    float32) against LAPACK's eigvalsh on the oracle's T~, for every vector of
+    256 channel groups: lambda = alpha / tau is at most 1e-5 above the exact
+    norm and at most `below` under it.  A Ritz value approaches the top
+    eigenvalue from below; at -4 dB twelve steps leave about one vector in
+    4,000 some 2e-5 short (a slightly larger tau), from 0 dB up all are within
+    1e-6.  With TAU_GIVEN, taser_run_tau returns the tau that was passed in,
+    bit for bit."""
+    import torch
+    G = 256
+    d = sim.gen_mimo(B, U, oracle.QPSK, G, YPH, snr, sim.seed_for(2, snr_index=int(snr) + 50))
+    H, y = _cuda(d["H"]), _cuda(d["y"])
+    alpha = 0.5
+    desc = gpu_lib.make_desc(G * YPH, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=alpha)
+    ws = torch.empty(gpu_lib.workspace_size(desc), dtype=torch.uint8, device="cuda")
+    gpu_lib.run_prep(desc, H, y, ws=ws)
+    tau = gpu_lib.run_tau(desc, ws).cpu().numpy().astype(np.float64)
+    Hv = np.repeat(d["H"], YPH, axis=0)
+    _, Tt, _ = oracle.precondition(oracle.build_T_coherent(Hv, d["y"], oracle.QPSK))
+    lam = oracle.spectral_norm(Tt)
+    rel = (alpha / tau - lam) / lam
+    assert rel.max() <= 1e-5, (rel.max(), int(rel.argmax()))
+    assert rel.min() >= -below, (rel.min(), int(rel.argmin()))
+    given = gpu_lib.make_desc(G * YPH, B, U, oracle.QPSK, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=YPH, t_max=10)
+    t_in = torch.rand(G * YPH, device="cuda", dtype=torch.float32) + 0.1
+    gpu_lib.run_prep(given, H, y, tau=t_in, ws=ws)
+    assert torch.equal(gpu_lib.run_tau(given, ws), t_in)
