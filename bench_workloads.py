@@ -30,8 +30,9 @@ def alpha_star(workload):
 
 
 def loop_flops(N, t_max):
+    """Algorithmic flops of t_max iterations (the same count as bench.py's)."""
     s2 = N * (N + 1) * (2 * N + 1) // 6
-    return t_max * (2 * s2 + 3 * N * (N + 1) // 2 + 2 * N)
+    return t_max * (2 * s2 + 2 * N * (N + 1) + 2 * N)
 
 
 def own_build_flops(B, U, N, mod):
