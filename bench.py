@@ -200,7 +200,9 @@ def main():
 
     cpu, oracle_sbar = None, {}
     if not args.no_cpu_baseline and not args.no_ber:
-        cpu, oracle_sbar = cpu_baseline(data, os.path.join(ROOT, "gpurun_out", "bench_tmp"))
+        import tempfile
+        with tempfile.TemporaryDirectory(prefix="taser_bench_") as workdir:
+            cpu, oracle_sbar = cpu_baseline(data, workdir)
 
     import torch
     import paper_1609_01797_amd as taser

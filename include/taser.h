@@ -54,7 +54,7 @@ typedef enum {
   TASER_OK = 0,
   TASER_ERR_ARG = -1,            /* null pointer, bad enum, bad alpha / t_max */
   TASER_ERR_SHAPE = -2,          /* sizes out of range or inconsistent */
-  TASER_ERR_UNSUPPORTED = -3,    /* valid request this build does not implement */
+  TASER_ERR_UNSUPPORTED = -3,    /* valid request the library does not implement */
   TASER_ERR_WORKSPACE = -4,      /* workspace pointer NULL or smaller than required */
   TASER_ERR_DEVICE = -5          /* a HIP call or kernel launch failed */
 } taser_status_t;
