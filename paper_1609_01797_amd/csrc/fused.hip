@@ -7,8 +7,8 @@
 // operand and stays in 16 VGPRs for the whole solve.  T~ is bordered:
 //     T~ = [ G~    c~_v ]      L~ = [ L11   0   ]
 //          [ c~_v^T  1  ]           [ l21^T l22 ]
-// Row i of V = L~ - tril(2 tau L~ T~) depends on row i of L~ only
-// (Algorithm 1, line 4), so the rows are processed one after another in
+// Row i of V = L~ - tril(2 tau L~ T~) (the gradient step of Algorithm 1)
+// depends on row i of L~ only, so the rows are processed one after another in
 // registers.  Register layout: lane l serves vector n = l % 16 and column
 // quad g = l / 16; for a row of L~ it holds columns 16 mt + 4 r + g
 // (mt in {0,1}, r in 0..3) in register (mt, r).  With the MFMA output rows
