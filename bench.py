@@ -102,6 +102,44 @@ def _oracle_chunk(args):
     return lo, np.concatenate(out, axis=0)
 
 
+def measured_peaks(torch, taser, stream):
+    """Rates this device reaches, for fractions against measured peaks beside
+    the datasheet ones: a device-to-device copy of 1 GiB (read + write bytes),
+    and the library's calibration kernels (float32 FMA on the vector ALUs,
+    BF16 and float32 MFMA), each launch about a millisecond, best of five."""
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    t = best(lambda: y.copy_(x))
+    out = {"hbm_copy_GBps": 2 * x.numel() * 4 / t / 1e9}
+    del x, y
+    buf = None
+    for kind, key, iters in ((0, "valu_fp32_fma_TFLOPs", 4096), (1, "mfma_bf16_TFLOPs", 4096),
+                             (2, "mfma_fp32_TFLOPs", 1024)):
+        fl = [0.0]
+
+        def launch():
+            nonlocal buf
+            buf, fl[0] = taser.calibrate(kind, iters, out=buf)
+        t = best(launch)
+        out[key] = fl[0] / t / 1e12
+    out["note"] = ("float32 FMA without packed math (the build disables it): half the 157.3 TFLOP/s "
+                   "datasheet figure is the reachable vector peak")
+    return out
+
+
 def cpu_baseline(data, workdir):
     """The FP64 oracle, unchanged, over every vector of the SNR sample, with
     single-threaded worker processes.  Runs before the GPU is touched."""
@@ -169,6 +207,9 @@ def main():
                          "estimation and detection, 262,144 blocks), coherent32x8 (1,000 vectors), "
                          "mixed (100,000 vectors over six (B, U, modulation) classes in one call), "
                          "unfolded64x16 (learned step sizes: training steps/s and BER vs depth)")
+    ap.add_argument("--counters", action="store_true",
+                    help="run each calibration kernel once and one headline step per product "
+                         "precision, then exit (the launches a --pmc counter pass reads)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 512 MiB (the reference for "
                          "scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -187,6 +228,21 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+        return
+
+    if args.counters:
+        import torch
+        import paper_1609_01797_amd as taser
+        buf = None
+        for kind, iters in ((0, 4096), (1, 4096), (2, 1024)):
+            buf, _ = taser.calibrate(kind, iters, out=buf)
+        d = sim.gen_mimo(B, U, MOD, NUM_H, Y_PER_H, SNR_TIMED, sim.seed_for(2, snr_index=int(SNR_TIMED) + 10))
+        H, y = torch.from_numpy(d["H"]).cuda(), torch.from_numpy(d["y"]).cuda()
+        for name, prec in PRECS:
+            desc = taser.make_desc(V, B, U, MOD, prec=prec, y_per_H=Y_PER_H, t_max=T_MAX, alpha=ALPHA)
+            taser.run_solve(desc, taser.run_prep(desc, H, y))
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_launches": 3, "steps": [p for p, _ in PRECS]}))
         return
 
     if args.workload != "coherent128x16":
@@ -333,11 +389,16 @@ def main():
                 "work": "bytes of H (shared by 16 vectors), y, decisions and status"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic_from_profile(src_hash, roof["kernel"])
+    peaks = measured_peaks(torch, taser, stream)
+    roof["peak_measured"] = peaks[{"alu": "valu_fp32_fma_TFLOPs", "hbm": "hbm_copy_GBps"}[roof["bound"]]]
+    roof["frac_measured"] = roof["achieved"] / roof["peak_measured"]
     fp32 = timing["fp32"]
     fp32_roof = {"bound": "mfma", "kernel": "solve_group_qpsk16<fp32>", "kernel_ms": fp32["solve_kernel_ms"],
                  "achieved": loop_flops(N, T_MAX) * V / (fp32["solve_kernel_ms"] * 1e-3) / 1e12,
                  "peak": PEAK["mfma_fp32"], "unit": "TFLOP/s"}
     fp32_roof["frac"] = fp32_roof["achieved"] / fp32_roof["peak"]
+    fp32_roof["peak_measured"] = peaks["mfma_fp32_TFLOPs"]
+    fp32_roof["frac_measured"] = fp32_roof["achieved"] / fp32_roof["peak_measured"]
     whole = (loop_flops(N, T_MAX) + build_flops(B, U, N, Y_PER_H)) * V
     fp32["whole_step_tflops"] = whole / (fp32["ms_per_step"] * 1e-3) / 1e12
     fp32["whole_step_frac_fp32_peak"] = fp32["whole_step_tflops"] / PEAK["mfma_fp32"]
@@ -376,6 +437,7 @@ def main():
                    "precision": "bf16 MFMA products with fp32 accumulation; fp32 prox, norms, "
                                 "preconditioning and step size"},
         "roofline": roof,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "paths": timing,
         "accuracy": accuracy,

@@ -188,6 +188,21 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
 taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws_bytes,
                              float* tau, void* stream);
 
+/* ---- Calibration ------------------------------------------------------
+
+   Measured device rates for roofline statements (no part of the detector).
+   taser_calibrate launches one kernel on `stream` that keeps every SIMD busy
+   with one instruction type: kind 0 float32 FMA on the vector ALUs, kind 1
+   v_mfma_f32_16x16x16_bf16, kind 2 v_mfma_f32_16x16x4_f32, `iters` loop trips
+   (1 .. 2^24).  out: device float32 [taser_calibrate_elements()], owned by
+   the caller, overwritten with values that depend on the work.  *flops
+   (host) receives the floating-point operations the launch performs; the
+   caller times it.  Errors: TASER_ERR_ARG (kind, iters, NULL pointers),
+   TASER_ERR_DEVICE. */
+taser_status_t taser_calibrate(int32_t kind, int32_t iters, float* out, double* flops,
+                               void* stream);
+int32_t taser_calibrate_elements(void);
+
 /* ---- Mixed-size batches ------------------------------------------------
 
    Coherent detection of V vectors of different sizes in one call: vector v

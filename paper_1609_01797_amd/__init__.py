@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "calibrate", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
            "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
 
@@ -101,6 +101,10 @@ def load():
     lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_tau.restype = ctypes.c_int
     lib.taser_run_tau.argtypes = [D, _P, ctypes.c_size_t, _P, _P]
+    lib.taser_calibrate.restype = ctypes.c_int
+    lib.taser_calibrate.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), _P]
+    lib.taser_calibrate_elements.restype = ctypes.c_int32
+    lib.taser_calibrate_elements.argtypes = []
     U = ctypes.POINTER(UnfoldedDesc)
     lib.taser_unfolded_sizes.restype = ctypes.c_int
     lib.taser_unfolded_sizes.argtypes = [U, ctypes.POINTER(ctypes.c_size_t),
@@ -354,6 +358,20 @@ def run_tau(desc: Desc, ws, device=None):
                            ctypes.c_size_t(ws.numel()), ctypes.c_void_p(tau.data_ptr()), _stream(dev))
     _raise(st)
     return tau
+
+
+def calibrate(kind: int, iters: int, out=None, device=None):
+    """Launch calibration kernel ``kind`` (0 float32 FMA, 1 BF16 MFMA, 2 float32
+    MFMA); returns (out tensor, flops of the launch).  The caller times it."""
+    torch = _torch()
+    lib = load()
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty(int(lib.taser_calibrate_elements()), dtype=torch.float32, device=dev)
+    fl = ctypes.c_double(0.0)
+    _raise(lib.taser_calibrate(int(kind), int(iters), ctypes.c_void_p(out.data_ptr()), ctypes.byref(fl),
+                               _stream(dev)))
+    return out, fl.value
 
 
 MIXED_STRIDE = 64

@@ -103,6 +103,24 @@ __device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
                                                  __builtin_bit_cast(h4, b), c, 0, 0, 0);
 }
 
+// One 16x16x32 product: the K slots of the two 16-column tiles (kt = 0, 1)
+// side by side, a = [a0, a1], b = [b0, b1].  On gfx950 it takes the cycles of
+// one 16x16x16 product for twice the work.
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ __forceinline__ f4 mfma32(u2 a0, u2 a1, u2 b0, u2 b1, f4 c) {
+  const u4 a = {a0[0], a0[1], a1[0], a1[1]}, b = {b0[0], b0[1], b1[0], b1[1]};
+  if constexpr (P == TASER_PREC_BF16) {
+    typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a),
+                                                   __builtin_bit_cast(b8, b), c, 0, 0, 0);
+  } else {
+    typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a),
+                                                  __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+  }
+}
+
 // Krylov dimension for ||T~||_2.  Twelve steps of the plain float32
 // recurrence from [c~; 1] bring the top Ritz value within 1e-6 of ||T~||_2 on
 // 128x16 channels from 0 dB up; at -4 dB about one vector in 4,000 is still
@@ -596,8 +614,7 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
       const u2 b1 = pack4<P>(l21[1][0], l21[1][1], l21[1][2], l21[1][3]);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        lacc[mt] = mfma16<P>(Ah[mt][0], b0, f4{0.f, 0.f, 0.f, 0.f});
-        lacc[mt] = mfma16<P>(Ah[mt][1], b1, lacc[mt]);
+        lacc[mt] = mfma32<P>(Ah[mt][0], Ah[mt][1], b0, b1, f4{0.f, 0.f, 0.f, 0.f});
       }
     } else {
 #pragma unroll
@@ -630,12 +647,14 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
         using C2 = std::integral_constant<int, 2>;
         using C3 = std::integral_constant<int, 3>;
         const u2 b0 = pack4<P>(Lv(C0{}, C0{}), Lv(C0{}, C1{}), Lv(C0{}, C2{}), Lv(C0{}, C3{}));
-        ring[SLOT][0] = mfma16<P>(Ah[0][0], b0, f4{0.f, 0.f, 0.f, 0.f});
         if constexpr (I >= 16) {
+          // both column tiles of the row are nonzero: one K = 32 product per
+          // output tile
           const u2 b1 = pack4<P>(Lv(C1{}, C0{}), Lv(C1{}, C1{}), Lv(C1{}, C2{}), Lv(C1{}, C3{}));
-          ring[SLOT][0] = mfma16<P>(Ah[0][1], b1, ring[SLOT][0]);
-          ring[SLOT][1] = mfma16<P>(Ah[1][0], b0, f4{0.f, 0.f, 0.f, 0.f});
-          ring[SLOT][1] = mfma16<P>(Ah[1][1], b1, ring[SLOT][1]);
+          ring[SLOT][0] = mfma32<P>(Ah[0][0], Ah[0][1], b0, b1, f4{0.f, 0.f, 0.f, 0.f});
+          ring[SLOT][1] = mfma32<P>(Ah[1][0], Ah[1][1], b0, b1, f4{0.f, 0.f, 0.f, 0.f});
+        } else {
+          ring[SLOT][0] = mfma16<P>(Ah[0][0], b0, f4{0.f, 0.f, 0.f, 0.f});
         }
         return;
       }

@@ -215,6 +215,17 @@ taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws
              : TASER_ERR_DEVICE;
 }
 
+taser_status_t taser_calibrate(int32_t kind, int32_t iters, float* out, double* flops,
+                               void* stream) {
+  if (kind < 0 || kind > 2 || iters < 1 || iters > (1 << 24) || !out || !flops)
+    return TASER_ERR_ARG;
+  return launch_calibrate(kind, iters, out, flops, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
+int32_t taser_calibrate_elements(void) { return calib_elements(); }
+
 static taser_status_t mixed_check(const taser_desc_t* d) {
   if (!d) return TASER_ERR_ARG;
   if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)

@@ -174,3 +174,15 @@ def test_unfolded_sizes_and_rejects():
                                        z) == taser.ERR_ARG
     empty = U(0, 9, 5, taser.REAL_F32, 2, 0)
     assert lib.taser_unfolded_forward(ctypes.byref(empty), z, z, z, z, z, z, z) == taser.OK
+
+
+def test_calibrate_rejects_bad_arguments():
+    lib = taser.load()
+    one = ctypes.c_void_p(16)   # never dereferenced: every call below fails first
+    fl = ctypes.c_double(0.0)
+    assert lib.taser_calibrate_elements() == 1024 * 256
+    assert lib.taser_calibrate(3, 10, one, ctypes.byref(fl), None) == taser.ERR_ARG
+    assert lib.taser_calibrate(-1, 10, one, ctypes.byref(fl), None) == taser.ERR_ARG
+    assert lib.taser_calibrate(0, 0, one, ctypes.byref(fl), None) == taser.ERR_ARG
+    assert lib.taser_calibrate(0, 10, None, ctypes.byref(fl), None) == taser.ERR_ARG
+    assert lib.taser_calibrate(0, 10, one, None, None) == taser.ERR_ARG

@@ -239,3 +239,16 @@ def test_fused_step_size_pin(gpu_lib, snr, below):
     t_in = torch.rand(G * YPH, device="cuda", dtype=torch.float32) + 0.1
     gpu_lib.run_prep(given, H, y, tau=t_in, ws=ws)
     assert torch.equal(gpu_lib.run_tau(given, ws), t_in)
+
+
+@pytest.mark.parametrize("kind, per_lane", [(0, 64.0), (1, 16 * 8192 / 64), (2, 16 * 2048 / 64)])
+def test_calibration_kernels(gpu_lib, kind, per_lane):
+    """The calibration kernels run, report the flops of their launch (per
+    lane and trip: 32 FMAs; 16 MFMAs of 16x16x16 or 16x16x4 per wave) and
+    leave finite values that depend on the work."""
+    import torch
+    out, fl = gpu_lib.calibrate(kind, 8)
+    torch.cuda.synchronize()
+    assert fl == pytest.approx(1024 * 256 * 8 * per_lane)
+    v = out.cpu().numpy()
+    assert np.all(np.isfinite(v)) and np.any(v != 0)
