@@ -135,8 +135,10 @@ def measured_peaks(torch, taser, stream):
             buf, fl[0] = taser.calibrate(kind, iters, out=buf)
         t = best(launch)
         out[key] = fl[0] / t / 1e12
-    out["note"] = ("float32 FMA without packed math (the build disables it): half the 157.3 TFLOP/s "
-                   "datasheet figure is the reachable vector peak")
+    out["note"] = ("float32 FMA without packed math (the build disables it); a wave64 float32 "
+                   "instruction issues in two cycles, so 157.3 TFLOP/s is the unpacked rate at full issue. "
+                   "The BF16 loop uses v_mfma_f32_16x16x16_bf16 (16 cycles each on gfx950, half the "
+                   "rate of the K = 32 forms)")
     return out
 
 
