@@ -10,7 +10,7 @@ namespace taser {
 namespace {
 
 constexpr int kBuildThreads = 256;
-constexpr int kLanczosMax = 24;      // Krylov dimension cap for ||T~||_2
+constexpr int kLanczosMax = 16;      // Krylov dimension cap for ||T~||_2
 constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
 
@@ -205,11 +205,29 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   if (tid < kWave) {
     const int lane = tid;
     const int m_cap = N < kLanczosMax ? N : kLanczosMax;
+    // Start: the last column of T~ (the dominant eigenvector weighs the last
+    // coordinate heavily, so few steps reach float32 resolution) plus 1 % of
+    // a vector without structural zeros, so that an eigenvector orthogonal
+    // to that column is still in the Krylov space.  Each lane reads and
+    // writes only its own entries of Q.
+    float nc = 0.f, ns = 0.f;
+    for (int r = lane; r < N; r += kWave) {
+      const float c = T[(size_t)r * N + N - 1], s = start_entry(r);
+      nc += c * c;
+      ns += s * s;
+    }
+    nc = wave_sum(nc);
+    ns = wave_sum(ns);
+    const float ic = nc > 0.f ? rsq(nc) : 0.f, is = 1e-2f * rsq(ns);
     float nrm = 0.f;
-    for (int r = lane; r < N; r += kWave) { const float s = start_entry(r); nrm += s * s; }
+    for (int r = lane; r < N; r += kWave) {
+      const float q = T[(size_t)r * N + N - 1] * ic + start_entry(r) * is;
+      Q[r] = q;
+      nrm += q * q;
+    }
     nrm = wave_sum(nrm);
     const float inv0 = rsq(nrm);
-    for (int r = lane; r < N; r += kWave) Q[r] = start_entry(r) * inv0;
+    for (int r = lane; r < N; r += kWave) Q[r] *= inv0;
     int m = 0;
     float scale = 0.f;
     for (int j = 0; j < m_cap; ++j) {
