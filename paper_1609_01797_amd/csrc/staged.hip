@@ -10,7 +10,11 @@ namespace taser {
 namespace {
 
 constexpr int kBuildThreads = 256;
-constexpr int kLanczosMax = 16;      // Krylov dimension cap for ||T~||_2
+// Krylov dimension cap for ||T~||_2: 16 steps when U <= B (the top
+// eigenvalue stands out; float32 resolution from -4 dB up), 24 for
+// overloaded systems (U > B), whose leading eigenvalues crowd together.
+constexpr int kLanczosMax = 24;
+constexpr int kLanczosWellPosed = 16;
 constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
 
@@ -204,7 +208,8 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   __shared__ float al[kLanczosMax], be2[kLanczosMax];
   if (tid < kWave) {
     const int lane = tid;
-    const int m_cap = N < kLanczosMax ? N : kLanczosMax;
+    const int m_lim = U <= B ? kLanczosWellPosed : kLanczosMax;
+    const int m_cap = N < m_lim ? N : m_lim;
     // Start: the last column of T~ (the dominant eigenvector weighs the last
     // coordinate heavily, so few steps reach float32 resolution) plus 1 % of
     // a vector without structural zeros, so that an eigenvector orthogonal

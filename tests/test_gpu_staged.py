@@ -73,6 +73,23 @@ def test_staged_coherent_spectral_tau(gpu_lib, case):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
 
+@pytest.mark.parametrize("B, U, mod, snr", [(128, 16, oracle.QPSK, -4.0), (64, 16, oracle.QPSK, 4.0),
+                                            (40, 64, oracle.BPSK, 20.0), (40, 64, oracle.BPSK, 0.0),
+                                            (16, 32, oracle.QPSK, 10.0)])
+def test_staged_lambda_pin(gpu_lib, B, U, mod, snr):
+    """||T~||_2 of the staged build (Lanczos from the last column of T~ with
+    full reorthogonalisation: 16 steps when U <= B, 24 for overloaded
+    systems) against LAPACK's eigvalsh, 1e-5 relative, at low SNR and for
+    overloaded channels."""
+    d = sim.gen_mimo(B, U, mod, 256, 1, snr, sim.seed_for(1, snr_index=int(snr) + 20, shard=U))
+    T = oracle.build_T_coherent(d["H"], d["y"], mod)
+    _, Tt, _ = oracle.precondition(T)
+    lam = oracle.spectral_norm(Tt)
+    desc = gpu_lib.make_desc(256, B, U, mod, t_max=1, alpha=0.5)
+    g = staged(gpu_lib, desc, d["H"], d["y"])
+    np.testing.assert_allclose(g["lam"], lam, rtol=1e-5)
+
+
 @pytest.mark.parametrize("mod,K,nb,t_max", [(oracle.QPSK, 16, 512, 20), (oracle.BPSK, 8, 300, 20),
                                             (oracle.QPSK, 3, 100, 5)])
 def test_staged_jed(gpu_lib, mod, K, nb, t_max):
