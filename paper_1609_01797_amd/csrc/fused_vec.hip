@@ -99,6 +99,11 @@ __device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 constexpr int kLanczos = 12;
+// Joint estimation and detection: T~ has one dominant eigenvalue (the
+// rank-one signal part of the received block), and six steps reach the
+// float32 resolution of ||T~||_2 from -2 dB up; later steps only add ghost
+// copies.  The remaining entries are parked like a breakdown.
+constexpr int kLanczosJed = 6;
 
 // Largest eigenvalue of the symmetric tridiagonal (al, b2 = beta^2), the same
 // in every lane, by 65-way multisection: in each round lane l tests the
@@ -406,8 +411,14 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     q32 *= inv0;
     bool done = false;
     float scale = 0.f;
+    const int steps = jed ? kLanczosJed : kLanczos;
     sfor<0, kLanczos>([&](auto jc) {
       constexpr int J = decltype(jc)::value;
+      if (J >= steps) {
+        al[J] = -1e30f;
+        b2[J] = 0.f;
+        return;
+      }
       gemv(Q, Wv);
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;

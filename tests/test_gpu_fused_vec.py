@@ -64,6 +64,19 @@ JED = [(oracle.QPSK, 16, 16, 600, 20), (oracle.BPSK, 16, 8, 400, 20), (oracle.QP
        (oracle.BPSK, 8, 32, 100, 12), (oracle.QPSK, 24, 30, 50, 10)]
 
 
+@pytest.mark.parametrize("snr", [-2.0, 0.0, 12.0])
+def test_vec_jed_spectral_low_snr(gpu_lib, snr):
+    """Joint detection with the kernel's own step size (six Lanczos steps from
+    T~ e_N) across the SNR range of the JED workload: L~ within 1e-5 of the
+    oracle, which uses LAPACK's ||T~||_2."""
+    d = sim.gen_jed(16, 16, oracle.QPSK, 400, snr, sim.seed_for(5, snr_index=int(snr) + 30))
+    ref = oracle.detect_jed(d["Y"], d["s0"], oracle.QPSK, alpha=0.5, t_max=20)
+    desc = gpu_lib.make_desc(400, 16, 16, oracle.QPSK, mode=gpu_lib.JED, t_max=20, alpha=0.5)
+    g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"])
+    assert_L_parity(unpack_lower(g["L"], 33), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
 @pytest.mark.parametrize("mod,Bx,K,nb,t_max", JED, ids=lambda x: str(x))
 def test_vec_jed(gpu_lib, mod, Bx, K, nb, t_max):
     d = sim.gen_jed(Bx, K, mod, nb, 6.0, sim.seed_for(5, shard=K + Bx))
