@@ -113,7 +113,7 @@ constexpr int kLanczosJed = 6;
 // The bracket is [max_k al_k, Gershgorin upper bound]: diagonal entries are
 // Rayleigh quotients, so the largest one bounds the top eigenvalue below.
 template <int M>
-__device__ __forceinline__ float top_eigenvalue(const float (&al)[M], const float (&b2)[M]) {
+__device__ __forceinline__ float top_eigenvalue(const float* al, const float* b2) {
   float lo = -3.4e38f, hi = -3.4e38f;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -454,7 +454,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       qp32 = q32;
       q32 = w32 * ib;
     });
-    const float lam = top_eigenvalue<kLanczos>(al, b2);
+    // the tridiagonal of the steps taken (JED: the leading 6 x 6 block)
+    const float lam = jed ? top_eigenvalue<kLanczosJed>(al, b2) : top_eigenvalue<kLanczos>(al, b2);
     tau = a.alpha / (lam > 0.f ? lam : 1.f);
   }
   const float m2tau = -2.f * tau;
