@@ -141,6 +141,17 @@ taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const floa
 taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const float* D,
                             int8_t* sbar, float* margin, void* stream);
 
+/* Channel estimate of joint estimation and detection (Section II-B, eq. (4)):
+   h = Y [s0; s_r] for every block, h_b = sum_k Y[k][b] s_k, where s_k (k >= 1)
+   are the detected data symbols read from sbar (QPSK s_k = sbar[k-1] +
+   j sbar[K+k-1], BPSK s_k = sbar[k-1]).  desc: a JED descriptor (U = K data
+   slots).  Y: complex64 [V][K+1][B] slot-major, s0: complex64 [V] pilots,
+   sbar: int8 [V][N-1] as written by taser_run / taser_detect, h: complex64
+   [V][B] (out); device memory owned by the caller.  Errors: those of
+   taser_check_desc, TASER_ERR_ARG (not JED, NULL pointers). */
+taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const void* s0,
+                                 const int8_t* sbar, void* h, void* stream);
+
 /* Device workspace (bytes) that taser_run needs for this descriptor, written
    to *bytes; 0 when the request needs none.  Host-only; returns the same
    errors as taser_run would for the descriptor (TASER_ERR_UNSUPPORTED for a

@@ -16,7 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
-           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "calibrate", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
+           "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "calibrate", "jed_channel", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
            "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
 
@@ -101,6 +101,8 @@ def load():
     lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_tau.restype = ctypes.c_int
     lib.taser_run_tau.argtypes = [D, _P, ctypes.c_size_t, _P, _P]
+    lib.taser_jed_channel.restype = ctypes.c_int
+    lib.taser_jed_channel.argtypes = [D, _P, _P, _P, _P, _P]
     lib.taser_calibrate.restype = ctypes.c_int
     lib.taser_calibrate.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double), _P]
     lib.taser_calibrate_elements.restype = ctypes.c_int32
@@ -231,6 +233,20 @@ def detect(desc: Desc, L, D, want_margin=True):
                           _stream(L.device))
     _raise(st)
     return sbar, margin
+
+
+def jed_channel(desc: Desc, Y, s0, sbar):
+    """Channel estimate h = Y [s0; s_r] of joint detection (eq. (4)) from the
+    detected symbols ``sbar`` [V, N-1]; returns complex64 [V, B]."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    h = torch.empty((V, desc.B), dtype=torch.complex64, device=Y.device)
+    st = lib.taser_jed_channel(ctypes.byref(desc), _need(Y, torch.complex64, V * (desc.U + 1) * desc.B, "Y"),
+                               _need(s0, torch.complex64, V, "s0"), _need(sbar, torch.int8, V * (N - 1), "sbar"),
+                               ctypes.c_void_p(h.data_ptr()), _stream(Y.device))
+    _raise(st)
+    return h
 
 
 def workspace_size(desc: Desc) -> int:

@@ -114,6 +114,19 @@ taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const floa
              : TASER_ERR_DEVICE;
 }
 
+taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const void* s0,
+                                 const int8_t* sbar, void* h, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  if (desc->mode != TASER_JED) return TASER_ERR_ARG;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!Y || !s0 || !sbar || !h) return TASER_ERR_ARG;
+  return launch_jed_channel(desc->num_vectors, desc->B, desc->U, desc->mod == TASER_QPSK, Y, s0,
+                            sbar, h, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? TASER_OK
+             : TASER_ERR_DEVICE;
+}
+
 static taser_status_t fused_args(const taser_desc_t* desc, FusedArgs* a) {
   taser_status_t st = check(desc);
   if (st != TASER_OK) return st;

@@ -55,6 +55,8 @@ hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_tau(const FusedArgs& a, float* tau, hipStream_t s);
 int calib_elements();
+hipError_t launch_jed_channel(int V, int B, int K, bool qpsk, const void* Y, const void* s0,
+                              const int8_t* sbar, void* h, hipStream_t s);
 hipError_t launch_calibrate(int kind, int iters, float* out, double* flops, hipStream_t s);
 
 // Mixed-size batches: per-vector sizes and offsets, and the bucket lists in

@@ -186,3 +186,15 @@ def test_calibrate_rejects_bad_arguments():
     assert lib.taser_calibrate(0, 0, one, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(0, 10, None, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(0, 10, one, None, None) == taser.ERR_ARG
+
+
+def test_jed_channel_rejects_bad_arguments():
+    lib = taser.load()
+    one = ctypes.c_void_p(16)   # never dereferenced: every call below fails first
+    coh = taser.make_desc(8, 16, 16, taser.QPSK)
+    jed = taser.make_desc(8, 16, 16, taser.QPSK, mode=taser.JED)
+    assert lib.taser_jed_channel(ctypes.byref(coh), one, one, one, one, None) == taser.ERR_ARG
+    assert lib.taser_jed_channel(ctypes.byref(jed), None, one, one, one, None) == taser.ERR_ARG
+    assert lib.taser_jed_channel(ctypes.byref(jed), one, one, one, None, None) == taser.ERR_ARG
+    empty = taser.make_desc(0, 16, 16, taser.QPSK, mode=taser.JED)
+    assert lib.taser_jed_channel(ctypes.byref(empty), None, None, None, None, None) == taser.OK

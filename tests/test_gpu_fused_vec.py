@@ -166,3 +166,24 @@ def test_vec_zero_norm_reset(gpu_lib):
     g = run_fused(gpu_lib, desc, H, y, tau=np.array([0.5], dtype=np.float32))
     assert g["status"][0] & gpu_lib.VEC_ZERO_NORM
     np.testing.assert_allclose(unpack_lower(g["L"], 5)[0], ref["L"][0], atol=1e-6)
+
+
+@pytest.mark.parametrize("mod, K, nb", [(oracle.QPSK, 16, 400), (oracle.BPSK, 8, 300), (oracle.QPSK, 3, 129)])
+def test_jed_channel_estimate(gpu_lib, mod, K, nb):
+    """taser_jed_channel: h = Y [s0; s_r] (eq. (4)) from the detected symbols,
+    against the oracle's estimate for every block whose decisions equal the
+    oracle's (float32 sum of K + 1 complex products: 1e-5 relative)."""
+    import torch
+    d = sim.gen_jed(16, K, mod, nb, 6.0, sim.seed_for(5, snr_index=40, shard=K))
+    ref = oracle.detect_jed(d["Y"], d["s0"], mod, alpha=0.5, t_max=20)
+    desc = gpu_lib.make_desc(nb, 16, K, mod, mode=gpu_lib.JED, t_max=20, alpha=0.5)
+    Y, s0 = _cuda(d["Y"]), _cuda(d["s0"])
+    res = gpu_lib.run(desc, None, Y, s0)
+    h = gpu_lib.jed_channel(desc, Y, s0, res["sbar"])
+    torch.cuda.synchronize()
+    sb, hg = res["sbar"].cpu().numpy(), h.cpu().numpy()
+    same = np.all(sb == ref["sbar"], axis=1)
+    assert same.mean() >= 0.99
+    hr = ref["h_hat"][same]
+    scale = np.abs(hr).max(axis=1, keepdims=True)
+    assert np.all(np.abs(hg[same] - hr) <= 1e-5 * scale + 1e-6)
