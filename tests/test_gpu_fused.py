@@ -144,7 +144,8 @@ def test_fused_degenerate_groups(gpu_lib):
     np.testing.assert_allclose(unpack_lower(g["L"][bad], N), ref["L"][bad], rtol=1e-6)
 
 
-@pytest.mark.parametrize("Bx,t_max,flags", [(30, 10, 0), (7, 3, 0), (128, 0, 0), (64, 8, 1)])
+@pytest.mark.parametrize("Bx,t_max,flags", [(30, 10, 0), (7, 3, 0), (128, 0, 0), (64, 8, 1),
+                                           (100, 10, 0), (45, 10, 0)])
 def test_fused_ragged_and_flags(gpu_lib, Bx, t_max, flags):
     d = sim.gen_mimo(Bx, U, oracle.QPSK, 8, 32, 8.0, 777 + Bx)
     ref = _group_oracle(d, 0.7, t_max, pin_last=not flags)
@@ -252,3 +253,18 @@ def test_calibration_kernels(gpu_lib, kind, per_lane):
     assert fl == pytest.approx(1024 * 256 * 8 * per_lane)
     v = out.cpu().numpy()
     assert np.all(np.isfinite(v)) and np.any(v != 0)
+
+
+@pytest.mark.parametrize("groups", [1, 5, 13])
+def test_fused_group_count_not_multiple_of_workgroup(gpu_lib, groups):
+    """Group counts that leave waves of the last preparation workgroup without
+    a channel group: those waves still take part in the workgroup barriers of
+    the step size (tau spectral) and store nothing; every vector matches the
+    oracle."""
+    d = sim.gen_mimo(B, U, oracle.QPSK, groups, YPH, 10.0, sim.seed_for(2, snr_index=60, shard=groups))
+    ref = _group_oracle(d, 0.5, 10)
+    desc = gpu_lib.make_desc(groups * YPH, B, U, oracle.QPSK, y_per_H=YPH, t_max=10, alpha=0.5)
+    g = fused(gpu_lib, desc, d["H"], d["y"])
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+    np.testing.assert_array_equal(g["status"], ref["status"])
