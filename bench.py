@@ -85,13 +85,16 @@ def sbar_of(s):
     return np.concatenate([s.real, s.imag], axis=1).astype(np.int8)
 
 
+L_SAMPLE = 1024   # vectors whose L~ the oracle returns for the L~ error statement
+
+
 def _oracle_chunk(args):
     lo, hi, Hpath, ypath = args
     from threadpoolctl import threadpool_limits
     import oracle
     H = np.load(Hpath, mmap_mode="r")
     y = np.load(ypath, mmap_mode="r")
-    out = []
+    out, Ls = [], []
     with threadpool_limits(1):
         for a in range(lo, hi, 1024):
             b = min(hi, a + 1024)
@@ -99,7 +102,9 @@ def _oracle_chunk(args):
             Hv = np.asarray(H[a // Y_PER_H: b // Y_PER_H]).repeat(Y_PER_H, axis=0)
             r = oracle.detect_coherent(Hv, np.asarray(y[a:b]), MOD, alpha=ALPHA, t_max=T_MAX)
             out.append(r["sbar"])
-    return lo, np.concatenate(out, axis=0)
+            if a < L_SAMPLE:
+                Ls.append(r["L"][:min(b, L_SAMPLE) - a])
+    return lo, np.concatenate(out, axis=0), (np.concatenate(Ls, axis=0) if Ls else None)
 
 
 def measured_peaks(torch, taser, stream):
@@ -150,7 +155,7 @@ def cpu_baseline(data, workdir):
     os.makedirs(workdir, exist_ok=True)
     step = (V + cores - 1) // cores
     step = ((step + Y_PER_H - 1) // Y_PER_H) * Y_PER_H
-    decisions = {}
+    decisions, L_ref = {}, {}
     total = 0.0
     with mp.get_context("fork").Pool(cores) as pool:
         for snr in SNR_ORACLE:
@@ -164,6 +169,7 @@ def cpu_baseline(data, workdir):
             total += time.perf_counter() - t0
             parts.sort(key=lambda p: p[0])
             decisions[snr] = np.concatenate([p[1] for p in parts], axis=0)
+            L_ref[snr] = np.concatenate([p[2] for p in parts if p[2] is not None], axis=0)[:L_SAMPLE]
             os.remove(Hpath)
             os.remove(ypath)
     n = V * len(SNR_ORACLE)
@@ -171,7 +177,7 @@ def cpu_baseline(data, workdir):
             "seconds": total,
             "sample": f"{len(SNR_ORACLE)} SNR points x {V} vectors of the workload "
                       f"(SNR dB {SNR_ORACLE}), FP64 numpy oracle with LAPACK eigvalsh for tau, "
-                      f"{cores} single-threaded worker processes"}, decisions
+                      f"{cores} single-threaded worker processes"}, decisions, L_ref
 
 
 def snr_at(snrs, bers, target):
@@ -256,11 +262,11 @@ def main():
     data = {snr: sim.gen_mimo(B, U, MOD, NUM_H, Y_PER_H, snr, sim.seed_for(2, snr_index=int(snr) + 10))
             for snr in snrs}
 
-    cpu, oracle_sbar = None, {}
+    cpu, oracle_sbar, oracle_L = None, {}, {}
     if not args.no_cpu_baseline and not args.no_ber:
         import tempfile
         with tempfile.TemporaryDirectory(prefix="taser_bench_") as workdir:
-            cpu, oracle_sbar = cpu_baseline(data, workdir)
+            cpu, oracle_sbar, oracle_L = cpu_baseline(data, workdir)
 
     import torch
     import paper_1609_01797_amd as taser
@@ -271,6 +277,8 @@ def main():
     # ---------------- accuracy sweep (paired inputs) ----------------
     ber = {name: [] for name, _ in PRECS}
     flips = {name: {} for name, _ in PRECS}
+    L_err = {name: {} for name, _ in PRECS}
+    tri_r, tri_c = np.tril_indices(N)
     for snr in snrs:
         d = data[snr]
         H = torch.from_numpy(d["H"]).to(dev)
@@ -278,10 +286,23 @@ def main():
         truth = sbar_of(d["s"])
         for name, prec in PRECS:
             desc = taser.make_desc(V, B, U, MOD, prec=prec, y_per_H=Y_PER_H, t_max=T_MAX, alpha=ALPHA)
-            sb = taser.run(desc, H, y)["sbar"].cpu().numpy()
+            want_L = snr in oracle_L
+            res = taser.run(desc, H, y, want_L=want_L)
+            sb = res["sbar"].cpu().numpy()
             ber[name].append(float(np.mean(sb != truth)))
             if snr in oracle_sbar:
                 flips[name][str(snr)] = int(np.count_nonzero(sb != oracle_sbar[snr]))
+            if want_L:
+                # per-vector ||L~_gpu - L~_64||_F / ||L~_64||_F on the first
+                # L_SAMPLE vectors (tau from each side's own spectral norm)
+                Lg = np.zeros((L_SAMPLE, N, N))
+                Lg[:, tri_r, tri_c] = res["L"][:L_SAMPLE].cpu().numpy()
+                Lr = oracle_L[snr]
+                e = np.linalg.norm((Lg - Lr).reshape(L_SAMPLE, -1), axis=1) / \
+                    np.linalg.norm(Lr.reshape(L_SAMPLE, -1), axis=1)
+                L_err[name][str(snr)] = {"max": float(e.max()), "p99.9": float(np.percentile(e, 99.9)),
+                                         "median": float(np.median(e))}
+                del res
     ber_fp64 = ([float(np.mean(oracle_sbar[s] != sbar_of(data[s]["s"]))) for s in SNR_ORACLE]
                 if oracle_sbar else [])
 
@@ -408,6 +429,8 @@ def main():
 
     accuracy = {"snr_db": snrs, "ber": ber, "bits_per_point": V * (N - 1),
                 "paired_bit_flips_vs_fp64": flips}
+    if any(L_err.values()):
+        accuracy["L_rel_err_vs_fp64"] = {"vectors": L_SAMPLE, "per_precision": L_err}
     if ber_fp64:
         accuracy["snr_db_fp64"] = SNR_ORACLE
         accuracy["ber"]["fp64"] = ber_fp64
