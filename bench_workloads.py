@@ -46,13 +46,25 @@ def own_build_flops(B, U, N, mod):
 
 
 def _oracle_sample(kind, d, idx, mod, t_max, alpha):
-    """Oracle decisions for the sampled vectors (single process: the sample
-    is bounded to a few seconds of CPU work)."""
+    """Oracle decisions and L~ for the sampled vectors (single process: the
+    sample is bounded to a few seconds of CPU work)."""
     import oracle
     if kind == "jed":
-        return oracle.detect_jed(d["Y"][idx], d["s0"][idx], mod, alpha=alpha, t_max=t_max)["sbar"]
-    Hv = np.repeat(d["H"], d["y_per_H"], axis=0)[idx]
-    return oracle.detect_coherent(Hv, d["y"][idx], mod, alpha=alpha, t_max=t_max)["sbar"]
+        r = oracle.detect_jed(d["Y"][idx], d["s0"][idx], mod, alpha=alpha, t_max=t_max)
+    else:
+        Hv = np.repeat(d["H"], d["y_per_H"], axis=0)[idx]
+        r = oracle.detect_coherent(Hv, d["y"][idx], mod, alpha=alpha, t_max=t_max)
+    return r["sbar"], r["L"]
+
+
+def _L_err(L_packed, L_ref):
+    """Per-vector ||L~_gpu - L~_64||_F / ||L~_64||_F: max, p99.9, median."""
+    n, N = L_ref.shape[0], L_ref.shape[-1]
+    Lg = np.zeros((n, N, N))
+    r, c = np.tril_indices(N)
+    Lg[:, r, c] = L_packed
+    e = np.linalg.norm((Lg - L_ref).reshape(n, -1), axis=1) / np.linalg.norm(L_ref.reshape(n, -1), axis=1)
+    return {"max": float(e.max()), "p99.9": float(np.percentile(e, 99.9)), "median": float(np.median(e))}
 
 
 def _time(fn, steps, warmup, stream):
@@ -319,7 +331,8 @@ def run_workload(args):
     rng = np.random.default_rng(12345)
     idx = np.sort(rng.choice(V, size=min(sample, V), replace=False))
     precs = (("bf16", 1), ("fp32", 0), ("fp16", 2))
-    res = {"paths": {}, "ber": {p: [] for p, _ in precs}, "ber_fp64_sample": [], "ber_sample": {p: [] for p, _ in precs}}
+    res = {"paths": {}, "ber": {p: [] for p, _ in precs}, "ber_fp64_sample": [], "ber_sample": {p: [] for p, _ in precs},
+           "L_err": {p: {} for p, _ in precs}}
     cpu_seconds = 0.0
     for snr in snrs:
         if kind == "jed":
@@ -331,7 +344,7 @@ def run_workload(args):
             truth = np.concatenate([d["s"].real, d["s"].imag], axis=1).astype(np.int8)
             ins = (torch.from_numpy(d["H"]).to(dev), torch.from_numpy(d["y"]).to(dev), None)
         t0 = time.perf_counter()
-        ref = _oracle_sample(kind, d, idx, mod, t_max, alpha)
+        ref, ref_L = _oracle_sample(kind, d, idx, mod, t_max, alpha)
         cpu_seconds += time.perf_counter() - t0
         res["ber_fp64_sample"].append(float(np.mean(ref != truth[idx])))
         for name, prec in precs:
@@ -343,6 +356,10 @@ def run_workload(args):
             sb = out["sbar"].cpu().numpy()
             res["ber"][name].append(float(np.mean(sb != truth)))
             res["ber_sample"][name].append(float(np.mean(sb[idx] != truth[idx])))
+            # L~ of the sampled vectors against the oracle's (an untimed call)
+            Lg = taser.run(desc, ins[0], ins[1], ins[2], want_L=True)["L"]
+            res["L_err"][name][str(snr)] = _L_err(Lg[torch.from_numpy(idx).to(dev)].cpu().numpy(), ref_L)
+            del Lg
             if snr == snr_timed:
                 ms = _time(fn, args.steps, args.warmup, stream)
                 res["paths"][name] = {"kernel_ms": ms, "per_s": V / (ms * 1e-3)}
@@ -367,5 +384,6 @@ def run_workload(args):
                              "kind": "oracle", "sample": f"{len(idx)} sampled vectors per SNR point x "
                              f"{len(snrs)} points, one process"},
             "accuracy": {"snr_db": snrs, "ber": res["ber"], "sample_size": int(len(idx)),
+                         "L_rel_err_vs_fp64": res["L_err"],
                          "ber_fp64_sample": res["ber_fp64_sample"], "ber_gpu_sample": res["ber_sample"]},
             "paths": res["paths"]}
