@@ -205,7 +205,7 @@ taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws
    taser_calibrate launches one kernel on `stream` that keeps every SIMD busy
    with one instruction type: kind 0 float32 FMA on the vector ALUs, kind 1
    v_mfma_f32_16x16x16_bf16, kind 2 v_mfma_f32_16x16x4_f32, `iters` loop trips
-   (1 .. 2^24).  out: device float32 [taser_calibrate_elements()], owned by
+   (1 .. 2^16).  out: device float32 [taser_calibrate_elements()], owned by
    the caller, overwritten with values that depend on the work.  *flops
    (host) receives the floating-point operations the launch performs; the
    caller times it.  Errors: TASER_ERR_ARG (kind, iters, NULL pointers),

@@ -230,7 +230,7 @@ taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws
 
 taser_status_t taser_calibrate(int32_t kind, int32_t iters, float* out, double* flops,
                                void* stream) {
-  if (kind < 0 || kind > 2 || iters < 1 || iters > (1 << 24) || !out || !flops)
+  if (kind < 0 || kind > 2 || iters < 1 || iters > (1 << 16) || !out || !flops)
     return TASER_ERR_ARG;
   return launch_calibrate(kind, iters, out, flops, static_cast<hipStream_t>(stream)) == hipSuccess
              ? TASER_OK

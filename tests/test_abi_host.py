@@ -184,6 +184,7 @@ def test_calibrate_rejects_bad_arguments():
     assert lib.taser_calibrate(3, 10, one, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(-1, 10, one, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(0, 0, one, ctypes.byref(fl), None) == taser.ERR_ARG
+    assert lib.taser_calibrate(0, (1 << 16) + 1, one, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(0, 10, None, ctypes.byref(fl), None) == taser.ERR_ARG
     assert lib.taser_calibrate(0, 10, one, None, None) == taser.ERR_ARG
 
