@@ -338,12 +338,17 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
 #pragma unroll 2
     for (int j = 0; j < kLanczosSteps; ++j) {
       f4 k1 = {0.f, 0.f, 0.f, 0.f}, k2 = k1, k3 = k1;
+      // issue priority while this wave feeds the matrix pipe (here and in the
+      // Gram below): the four waves of a SIMD otherwise leave it idle while
+      // they all run vector-ALU work
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         k1 = mfma(Apm[s], Q[0][s], k1);
         k2 = mfma(A[0][0][s], Q[1][s] - Q[0][s], k2);
         k3 = mfma(A[1][0][s], Q[0][s] + Q[1][s], k3);
       }
+      __builtin_amdgcn_s_setprio(0);
       float W[2][4];
       float cq = 0.f;
 #pragma unroll
@@ -508,11 +513,19 @@ __global__ __launch_bounds__(64 * kPrepWaves) void prep_group_qpsk16(FusedArgs a
   for (int r0 = 0; r0 < B; r0 += 8 * kQ) {
     if (r0 + 4 * kQ < B) load_batch(r0 + 4 * kQ, h1, y1);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) gram_rowquad(h0[q], y0[q], reG, pG, k1, k2, k3, ysq);
+    for (int q = 0; q < kQ; ++q) {
+      __builtin_amdgcn_s_setprio(1);
+      gram_rowquad(h0[q], y0[q], reG, pG, k1, k2, k3, ysq);
+      __builtin_amdgcn_s_setprio(0);
+    }
     if (r0 + 4 * kQ >= B) break;
     if (r0 + 8 * kQ < B) load_batch(r0 + 8 * kQ, h0, y0);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) gram_rowquad(h1[q], y1[q], reG, pG, k1, k2, k3, ysq);
+    for (int q = 0; q < kQ; ++q) {
+      __builtin_amdgcn_s_setprio(1);
+      gram_rowquad(h1[q], y1[q], reG, pG, k1, k2, k3, ysq);
+      __builtin_amdgcn_s_setprio(0);
+    }
   }
   prep_finish(a, grp, active, reG, pG, k1 + k3, k1 + k2, ysq);
 }
@@ -693,7 +706,13 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
     sfor<0, kAhead>([&](auto ic) { product(ic); });
     sfor<0, 32>([&](auto ic) {
       constexpr int I = decltype(ic)::value;
-      if constexpr (I + kAhead < 32) product(std::integral_constant<int, I + kAhead>{});
+      // the wave issuing its next row's MFMAs gets issue priority over a
+      // wave in its vector-ALU epilogue, which keeps the matrix pipe fed
+      if constexpr (I + kAhead < 32) {
+        __builtin_amdgcn_s_setprio(1);
+        product(std::integral_constant<int, I + kAhead>{});
+        __builtin_amdgcn_s_setprio(0);
+      }
       epilogue(ic);
     });
 
