@@ -230,6 +230,10 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const float2 h0 = hc[q][0], y = yc[q];
+      // float32 products: issue priority while this wave feeds the matrix
+      // pipe (here and in the tril products below); with 16-bit products it
+      // made mixed batches slower
+      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
       gre[0] = mfma(h0.x, h0.x, gre[0]);       // Re G = Hr^T Hr + Hi^T Hi
       gre[0] = mfma(h0.y, h0.y, gre[0]);
       gim[0] = mfma(h0.x, h0.y, gim[0]);       // Im G = Hr^T Hi - Hi^T Hr
@@ -247,6 +251,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
           gim[2] = mfma(h1.y, -h1.x, gim[2]);
         }
       }
+      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
       for (int t = 0; t < UTM; ++t) {          // conj(h) y
         bre[t] = fmaf(hc[q][t].x, y.x, fmaf(hc[q][t].y, y.y, bre[t]));
@@ -508,6 +513,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     sfor<0, NT>([&](auto ic) {
       constexpr int IT = decltype(ic)::value;
       f4 acc[IT + 1];
+      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
       if constexpr (k16) {
         u2 bk[IT + 1];
         sfor<0, IT + 1>([&](auto kc) {
@@ -533,6 +539,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
           });
         });
       }
+      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(0);
       sfor<0, IT + 1>([&](auto jc) {
         constexpr int JT = decltype(jc)::value;
 #pragma unroll
