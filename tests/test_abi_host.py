@@ -142,6 +142,24 @@ def test_mixed_entry_rejects_bad_arguments():
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
 
 
+def test_fused_entry_points_accept_an_empty_batch():
+    """V = 0 is a valid request with nothing to do: every fused entry point
+    returns OK with null buffers and starts no device work."""
+    lib = taser.load()
+    z = ctypes.c_void_p(0)
+    for mode, B, U, yph in ((taser.COHERENT, 128, 16, 16), (taser.COHERENT, 32, 8, 1), (taser.JED, 16, 16, 1)):
+        d = taser.make_desc(0, B, U, taser.QPSK, mode=mode, y_per_H=yph, t_max=10)
+        assert lib.taser_run(ctypes.byref(d), z, z, z, z, z, z, z, z, z, 0, z) == taser.OK
+    head = taser.make_desc(0, 128, 16, taser.QPSK, y_per_H=16, t_max=10)
+    assert lib.taser_run_prep(ctypes.byref(head), z, z, z, z, z, z, 0, z) == taser.OK
+    assert lib.taser_run_solve(ctypes.byref(head), z, z, z, z, z, 0, z) == taser.OK
+    assert lib.taser_run_tau(ctypes.byref(head), z, 0, z, z) == taser.OK
+    mixed = taser.make_desc(0, 1, 1, taser.QPSK, t_max=10)
+    launch = taser.MixedLaunch()
+    assert lib.taser_run_mixed(ctypes.byref(mixed), *([z] * 7), z, z, z, 64, z, ctypes.byref(launch),
+                               z, 0, z) == taser.OK
+
+
 def test_unfolded_sizes_and_rejects():
     """Shape and argument checks of the unfolded entry points run on the
     host before any device call."""
