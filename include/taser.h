@@ -49,6 +49,8 @@ extern "C" {
 
 #define TASER_ABI_VERSION 1
 #define TASER_MAX_N 129          /* largest problem size N the library accepts */
+#define TASER_MAX_VECTORS (1 << 30) /* largest num_vectors any entry point accepts
+                                       (kernel indices stay within 32 bits) */
 
 typedef enum {
   TASER_OK = 0,
@@ -77,7 +79,8 @@ enum { TASER_TAU_SPECTRAL = 0,   /* tau = alpha / ||T~||_2 (Algorithm 1 inputs) 
 #define TASER_VEC_UNSUPPORTED 16 /* mixed batch: no fused kernel for this size; decisions +1 */
 
 typedef struct {
-  int32_t num_vectors;  /* V >= 0: received vectors (coherent) or blocks (JED) */
+  int32_t num_vectors;  /* 0 <= V <= TASER_MAX_VECTORS: received vectors
+                           (coherent) or blocks (JED) */
   int32_t B;            /* receive antennas, >= 1 */
   int32_t U;            /* coherent: users; JED: K, the data slots after the pilot */
   int32_t mod;          /* TASER_BPSK or TASER_QPSK */
@@ -256,7 +259,7 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* B, const
 enum { TASER_REAL_F32 = 0, TASER_REAL_F64 = 1 };
 
 typedef struct {
-  int32_t num_vectors;  /* V */
+  int32_t num_vectors;  /* V, 0..TASER_MAX_VECTORS */
   int32_t N;            /* problem size, 2..64 */
   int32_t t_max;        /* iterations, 1..10000 */
   int32_t real;         /* TASER_REAL_* */

@@ -24,7 +24,8 @@ taser_status_t check(const taser_desc_t* d) {
   if (!valid_enums(d)) return TASER_ERR_ARG;
   if (d->t_max < 0 || d->t_max > 100000) return TASER_ERR_ARG;
   if (d->tau_mode == TASER_TAU_SPECTRAL && !(d->alpha > 0.f && d->alpha < 1.f)) return TASER_ERR_ARG;
-  if (d->num_vectors < 0 || d->B < 1 || d->U < 1) return TASER_ERR_SHAPE;
+  if (d->num_vectors < 0 || d->num_vectors > TASER_MAX_VECTORS || d->B < 1 || d->U < 1)
+    return TASER_ERR_SHAPE;
   const int N = taser_problem_size(d->U, d->mod);
   if (N < 2 || N > TASER_MAX_N) return TASER_ERR_SHAPE;
   if (d->y_per_H < 1) return TASER_ERR_SHAPE;
@@ -248,7 +249,7 @@ static taser_status_t mixed_check(const taser_desc_t* d) {
   if (d->t_max < 0 || d->t_max > 100000) return TASER_ERR_ARG;
   if (d->tau_mode == TASER_TAU_SPECTRAL && !(d->alpha > 0.f && d->alpha < 1.f)) return TASER_ERR_ARG;
   if (d->mode != TASER_COHERENT) return TASER_ERR_UNSUPPORTED;
-  if (d->num_vectors < 0) return TASER_ERR_SHAPE;
+  if (d->num_vectors < 0 || d->num_vectors > TASER_MAX_VECTORS) return TASER_ERR_SHAPE;
   return TASER_OK;
 }
 
@@ -297,7 +298,8 @@ static taser_status_t unf_check(const taser_unfolded_t* u) {
   if (!u) return TASER_ERR_ARG;
   if (u->real != TASER_REAL_F32 && u->real != TASER_REAL_F64) return TASER_ERR_ARG;
   if (u->flags & ~TASER_FLAG_LITERAL_LAST) return TASER_ERR_ARG;
-  if (u->num_vectors < 0 || u->N < 2 || u->N > 64) return TASER_ERR_SHAPE;
+  if (u->num_vectors < 0 || u->num_vectors > TASER_MAX_VECTORS || u->N < 2 || u->N > 64)
+    return TASER_ERR_SHAPE;
   if (u->t_max < 1 || u->t_max > 10000 || u->ckpt_every < 1) return TASER_ERR_SHAPE;
   UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
   if (unfolded_lds_bytes(a) > 163840) return TASER_ERR_UNSUPPORTED;

@@ -54,6 +54,8 @@ def _d(**kw):
     (dict(alpha=float("nan")), taser.ERR_ARG),
     (dict(alpha=2.0, tau_mode=taser.TAU_GIVEN), taser.OK),
     (dict(V=-1), taser.ERR_SHAPE),
+    (dict(V=1 << 30), taser.OK),            # TASER_MAX_VECTORS
+    (dict(V=(1 << 30) + 16), taser.ERR_SHAPE),
     (dict(B=0), taser.ERR_SHAPE),
     (dict(U=0), taser.ERR_SHAPE),
     (dict(U=65), taser.ERR_SHAPE),          # N = 131 > TASER_MAX_N
@@ -129,6 +131,8 @@ def test_mixed_entry_rejects_bad_arguments():
     n = ctypes.c_size_t(0)
     assert lib.taser_mixed_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
     assert n.value >= 3 * 10 * 4
+    big = taser.make_desc((1 << 30) + 1, 1, 1, taser.QPSK, t_max=10)
+    assert lib.taser_mixed_workspace_size(ctypes.byref(big), ctypes.byref(n)) == taser.ERR_SHAPE
     jd = taser.make_desc(10, 1, 1, taser.QPSK, mode=taser.JED)
     assert lib.taser_mixed_workspace_size(ctypes.byref(jd), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
     launch = taser.MixedLaunch()
@@ -175,6 +179,7 @@ def test_unfolded_sizes_and_rejects():
     assert sizes(U(3, 9, 5, taser.REAL_F64, 2, taser.FLAG_LITERAL_LAST)) == taser.OK
     assert (ck.value, ws.value) == (3 * 3 * 45, 3 * 5 * 8)
     assert sizes(U(1, 65, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
+    assert sizes(U((1 << 30) + 1, 9, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
     assert sizes(U(1, 1, 5, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
     assert sizes(U(1, 9, 0, taser.REAL_F32, 1, 0)) == taser.ERR_SHAPE
     assert sizes(U(1, 9, 5, taser.REAL_F32, 0, 0)) == taser.ERR_SHAPE
