@@ -27,6 +27,30 @@ def fused(taser, desc, H, y, tau=None, want_L=True):
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
+def _assert_prox_invariants(Lp, H, y, y_per_H, tol=2e-5):
+    """Properties of every vector's final L~ that hold at any batch size
+    (Section III-C, Algorithm 1): after the prox each column k < N has the
+    norm D_kk = sqrt(T_kk), and T_kk is the squared norm of the user's
+    channel column (the same for its real and imaginary coordinate); the
+    held last column is L~_NN = D_NN = ||y||.  The references are those
+    definitions in float64, not the oracle."""
+    hn = np.linalg.norm(H.astype(np.complex128), axis=1)          # [num_H, U]
+    Dref = np.concatenate([hn, hn], axis=1)                         # [num_H, N - 1]
+    yn = np.linalg.norm(y.astype(np.complex128), axis=1)            # [V]
+    r, c = np.tril_indices(N)
+    worst = 0.0
+    for v0 in range(0, Lp.shape[0], 8192):
+        v1 = min(v0 + 8192, Lp.shape[0])
+        L = np.zeros((v1 - v0, N, N))
+        L[:, r, c] = Lp[v0:v1]
+        norms = np.linalg.norm(L, axis=1)                           # column norms [n, N]
+        D = Dref[np.arange(v0, v1) // y_per_H]
+        err = np.abs(norms[:, :N - 1] / D - 1.0)
+        errN = np.abs(L[:, N - 1, N - 1] / yn[v0:v1] - 1.0)
+        worst = max(worst, float(err.max()), float(errN.max()))
+    assert worst <= tol, f"column norm / D_kk off by {worst:.3e}"
+
+
 def _group_oracle(d, alpha, t_max, tau=None, idx=None, pin_last=True):
     Hv = np.repeat(d["H"], d["y_per_H"], axis=0)
     y = d["y"]
@@ -71,7 +95,8 @@ def test_fused_full_batch_bench_configuration(gpu_lib, prec):
     t_max = 10, the swept alpha, taser_run_prep + taser_run_solve with a
     workspace, no L output.  Decisions are checked on a random sample of
     2,048 vectors against the oracle; L~ on the same sample from a second
-    launch that also writes L~."""
+    launch that also writes L~, and the prox's column norms on every
+    vector."""
     import torch
     alpha = _alpha_star()
     d = sim.gen_mimo(B, U, oracle.QPSK, 4096, YPH, 10.0, sim.seed_for(2, snr_index=5))
@@ -91,6 +116,7 @@ def test_fused_full_batch_bench_configuration(gpu_lib, prec):
     g2 = fused(gpu_lib, desc, d["H"], d["y"], want_L=True)
     np.testing.assert_array_equal(g2["sbar"], g["sbar"])
     assert_L_parity(unpack_lower(g2["L"][idx], N), ref["L"], tol=ltol)
+    _assert_prox_invariants(g2["L"], d["H"], d["y"], YPH)
 
 
 def test_fused_graph_replay(gpu_lib):
