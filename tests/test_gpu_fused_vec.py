@@ -104,11 +104,39 @@ def test_vec_jed_16bit(gpu_lib, prec):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=mtol)
 
 
+def _assert_jed_prox_invariants(Lp, Y, s0, tol=2e-5):
+    """Properties of every block's final L~ (Section II-B, III-C,
+    Algorithm 1): T = -A^T A with A = [Hbar, ybar], so D_kk = sqrt(|T_kk|)
+    is the norm of column k of A, i.e. the norm of data slot k's received
+    vector (for both coordinates of a QPSK symbol), and D_NN = ||y_0 s_0||;
+    after the prox every column of L~ has norm D_kk and L~_NN = D_NN.  The
+    references are those definitions in float64, not the oracle."""
+    Yc = Y.astype(np.complex128)
+    K = Y.shape[1] - 1
+    slot = np.linalg.norm(Yc[:, 1:, :], axis=2)                    # [nb, K]
+    N = 2 * K + 1
+    Dref = np.concatenate([slot, slot], axis=1)                    # [nb, N - 1]
+    DN = np.linalg.norm(Yc[:, 0, :], axis=1) * np.abs(s0.astype(np.complex128))
+    r, c = np.tril_indices(N)
+    worst = 0.0
+    for v0 in range(0, Lp.shape[0], 8192):
+        v1 = min(v0 + 8192, Lp.shape[0])
+        L = np.zeros((v1 - v0, N, N))
+        L[:, r, c] = Lp[v0:v1]
+        norms = np.linalg.norm(L, axis=1)
+        err = np.abs(norms[:, :N - 1] / Dref[v0:v1] - 1.0)
+        errN = np.abs(L[:, N - 1, N - 1] / DN[v0:v1] - 1.0)
+        worst = max(worst, float(err.max()), float(errN.max()))
+    assert worst <= tol, f"column norm / D_kk off by {worst:.3e}"
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "bf16"])
 def test_vec_jed_full_batch_bench_configuration(gpu_lib, prec):
     """The benchmark's joint-detection launch: 262,144 blocks, B = 16,
     K = 16 + pilot, t_max = 20, the swept alpha, tau spectral.  Decisions are
-    checked against the oracle on 2,048 sampled blocks."""
+    checked against the oracle on 2,048 sampled blocks; a second launch that
+    also writes L~ must repeat them, and the prox's column norms are checked
+    on every block."""
     import json
     import os
     alpha = float(json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alpha_star.json")))
@@ -125,6 +153,11 @@ def test_vec_jed_full_batch_bench_configuration(gpu_lib, prec):
     ref = oracle.detect_jed(d["Y"][idx], d["s0"][idx], oracle.QPSK, alpha=alpha, t_max=20)
     mtol = 1e-4 if prec == 0 else PREC_TOL[prec][1]
     assert_decisions(sb[idx], ref["sbar"], ref["margin"], tol=mtol)
+    del res
+    res = gpu_lib.run(desc, None, _cuda(d["Y"]), _cuda(d["s0"]), want_L=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(res["sbar"].cpu().numpy(), sb)
+    _assert_jed_prox_invariants(res["L"].cpu().numpy(), d["Y"], d["s0"])
 
 
 def test_vec_degenerate_and_flags(gpu_lib):
