@@ -660,9 +660,17 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   }
 }
 
+// Waves per SIMD the two-tile kernels (N - 1 <= 32) are compiled for: five
+// fit in 96 VGPRs without spilling (the unconstrained build takes 102, i.e.
+// four waves), and the extra wave hides more of the latency of each step's
+// dependency chain.  Six would need 80 and spill.
+template <int NT>
+constexpr int kVecWaves = NT == 2 ? 5 : 1;
+
 // One vector per block (uniform sizes).
 template <int NT, int P>
-__global__ __launch_bounds__(64) void fused_vec(FusedArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kVecWaves<NT>)))
+void fused_vec(FusedArgs a) {
   __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
   VecJob job;
   job.v = blockIdx.x;
@@ -723,7 +731,8 @@ __global__ __launch_bounds__(64) void fused_vec_mixed(FusedArgs a, MixedArgs m, 
 // (the loop made the compiler keep loop-invariant index arithmetic live
 // through every vector: 198 instead of 107 VGPRs for N-1 <= 32).
 template <int NT, int P>
-__global__ __launch_bounds__(64) void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kVecWaves<NT>)))
+void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
   __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
   const int item = blockIdx.x;
   if (item >= m.count[bucket]) return;
