@@ -573,6 +573,12 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) mdiag[d] = g <= d ? m2tau : 0.f;
   constexpr bool k16 = P != TASER_PREC_F32;
+  // float32 path: [V0; V1] = [R -M; M R] [a; b] is the complex product
+  // (R + jM)(a + jb), formed with three real products (Gauss):
+  // P1 = R a, P2 = M b, P3 = (R + M)(a + b); V0 = P1 - P2, V1 = P3 - P1 - P2.
+  float Apm[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) Apm[s] = A[0][0][s] + A[1][0][s];
   u2 Ah[2][2];
   if constexpr (k16) {
 #pragma unroll
@@ -630,14 +636,15 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
         lacc[mt] = mfma32<P>(Ah[mt][0], Ah[mt][1], b0, b1, f4{0.f, 0.f, 0.f, 0.f});
       }
     } else {
+      f4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        lacc[mt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) lacc[mt] = mfma(A[mt][kt][s], l21[kt][s], lacc[mt]);
+      for (int s = 0; s < 4; ++s) {
+        p1 = mfma(A[0][0][s], l21[0][s], p1);
+        p2 = mfma(A[1][0][s], l21[1][s], p2);
+        p3 = mfma(Apm[s], l21[0][s] + l21[1][s], p3);
       }
+      lacc[0] = p1 - p2;
+      lacc[1] = p3 - p1 - p2;
     }
     float cl = 0.f;
 #pragma unroll
@@ -671,20 +678,29 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
         }
         return;
       }
-      sfor<0, 2>([&](auto mc) {
-        constexpr int MT = decltype(mc)::value;
-        if constexpr (16 * MT <= I) {
-          ring[SLOT][MT] = f4{0.f, 0.f, 0.f, 0.f};
-          sfor<0, 2>([&](auto kc) {
-            constexpr int KT = decltype(kc)::value;
-            sfor<0, 4>([&](auto sc) {
-              constexpr int S = decltype(sc)::value;
-              if constexpr (16 * KT + 4 * S <= I)
-                ring[SLOT][MT] = mfma(A[MT][KT][S], Lr[I][KT][S], ring[SLOT][MT]);
-            });
-          });
-        }
-      });
+      if constexpr (I < 16) {
+        // one column tile: V0 = R a over the K-steps at or below the diagonal
+        ring[SLOT][0] = f4{0.f, 0.f, 0.f, 0.f};
+        sfor<0, 4>([&](auto sc) {
+          constexpr int S = decltype(sc)::value;
+          if constexpr (4 * S <= I) ring[SLOT][0] = mfma(A[0][0][S], Lr[I][0][S], ring[SLOT][0]);
+        });
+      } else {
+        // a = tile 0 (full), b = tile 1 (K-steps up to the diagonal)
+        f4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+        sfor<0, 4>([&](auto sc) {
+          constexpr int S = decltype(sc)::value;
+          p1 = mfma(A[0][0][S], Lr[I][0][S], p1);
+          if constexpr (16 + 4 * S <= I) {
+            p2 = mfma(A[1][0][S], Lr[I][1][S], p2);
+            p3 = mfma(Apm[S], Lr[I][0][S] + Lr[I][1][S], p3);
+          } else {
+            p3 = mfma(Apm[S], Lr[I][0][S], p3);
+          }
+        });
+        ring[SLOT][0] = p1 - p2;
+        ring[SLOT][1] = p3 - p1 - p2;
+      }
     };
     auto epilogue = [&](auto ic) {
       constexpr int I = decltype(ic)::value;
