@@ -238,6 +238,11 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
         return
 
+    if args.counters and args.workload != "coherent128x16":
+        from bench_workloads import run_counters
+        print(json.dumps(run_counters(args)))
+        return
+
     if args.counters:
         import torch
         import paper_1609_01797_amd as taser

@@ -129,7 +129,7 @@ def run_mixed_workload(args):
         out = {}
         call = lambda blocks=None: taser.run_mixed(desc, *ins, blocks=blocks, out=out, ws=ws)  # noqa: E731
         ms_default = _time(lambda: call(None), args.steps, args.warmup, stream)
-        best, best_ms, _, trace = autotune.tune_mixed(desc, ins, reps=3)
+        best, tune_report, trace = autotune.tune_mixed(desc, ins, reps=3)
         ms_tuned = _time(lambda: call(best), args.steps, args.warmup, stream)
         # graph replay of the tuned call
         call(best)
@@ -145,7 +145,8 @@ def run_mixed_workload(args):
             fl += int(np.count_nonzero(sb[idx, :rsb.shape[1]] != rsb))
         flips[name] = fl
         paths[name] = {"ms_default": ms_default, "ms_tuned": ms_tuned, "ms_graph": ms_graph,
-                       "tuned_blocks": best, "vectors_per_s": V / (min(ms_tuned, ms_graph) * 1e-3),
+                       "tuned_blocks": best, "autotune": tune_report,
+                       "vectors_per_s": V / (min(ms_tuned, ms_graph) * 1e-3),
                        "ber": err / int(mask.sum())}
     # algorithmic flops per vector, averaged over the batch
     fl_total = 0.0
@@ -308,6 +309,33 @@ def run_unfolded_workload(args):
                              "train_seconds": train_s,
                              "smallest_depth_matching_plain_t20": smallest_depth("plain_t20"),
                              "smallest_depth_matching_plain_t10": smallest_depth("plain_t10")}}
+
+
+def run_counters(args):
+    """One launch per product precision of a secondary workload, nothing
+    else: the launches a rocprofv3 --pmc counter pass reads."""
+    import torch
+    import paper_1609_01797_amd as taser
+    dev = torch.device("cuda:0")
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    precs = (("bf16", 1), ("fp32", 0), ("fp16", 2))
+    if args.workload == "jed16x16":
+        d = sim.gen_jed(16, 16, 2, 262144, 6.0, sim.seed_for(5, snr_index=6))
+        Y, s0 = cu(d["Y"]), cu(d["s0"])
+        for _, prec in precs:
+            desc = taser.make_desc(262144, 16, 16, 2, mode=taser.JED, prec=prec, t_max=20,
+                                   alpha=alpha_star("jed16x16"))
+            taser.run(desc, None, Y, s0)
+    elif args.workload == "mixed":
+        d = sim.gen_mixed(100000, 12.0, sim.seed_for(3, snr_index=6))
+        ins = [cu(d[k]) for k in ("B", "U", "mod", "H_off", "y_off", "H_flat", "y_flat")]
+        for _, prec in precs:
+            desc = taser.make_desc(100000, 1, 1, 2, prec=prec, t_max=10, alpha=alpha_star("mixed"))
+            taser.run_mixed(desc, *ins)
+    else:
+        raise SystemExit(f"--counters is not defined for --workload {args.workload}")
+    torch.cuda.synchronize()
+    return {"workload": args.workload, "launches": [p for p, _ in precs]}
 
 
 def run_workload(args):

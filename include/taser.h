@@ -97,6 +97,13 @@ typedef struct {
 /* Version of this ABI (TASER_ABI_VERSION of the built library). */
 int taser_abi_version(void);
 
+/* Testing aid for callers' error paths: the next `count` calls of entry
+   points that launch device work return TASER_ERR_DEVICE after their
+   argument checks and before they launch anything (count = 0 clears it).
+   Host-only and process-wide; argument and shape errors still take
+   precedence.  Errors: TASER_ERR_ARG for count < 0. */
+taser_status_t taser_debug_inject_device_error(int32_t count);
+
 /* Static text for a taser_status_t value. */
 const char* taser_status_string(int status);
 
@@ -156,24 +163,33 @@ taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const 
                                  const int8_t* sbar, void* h, void* stream);
 
 /* Device workspace (bytes) that taser_run needs for this descriptor, written
-   to *bytes; 0 when the request needs none.  Host-only; returns the same
-   errors as taser_run would for the descriptor (TASER_ERR_UNSUPPORTED for a
-   shape the fused path does not cover). */
+   to *bytes: 5,888 bytes per 16 vectors on the group path, 0 on the
+   per-vector path.  Host-only; returns the same errors as taser_run would
+   for the descriptor (TASER_ERR_UNSUPPORTED for a shape neither path
+   covers). */
 taser_status_t taser_workspace_size(const taser_desc_t* desc, size_t* bytes);
 
 /* The whole detector (build T, precondition, step size, t_max iterations,
-   slicing) in one call: two kernels on `stream`, a preprocessing kernel that
-   leaves each channel group's preconditioned G~, border c~, D and tau in the
-   workspace, and the solve kernel that keeps L~ in registers.
+   slicing) in one call, with T~ and L~ kept on chip.  Two kernel families
+   serve it, chosen from the descriptor:
+     group path: coherent QPSK with U = 16 (N = 33) and y_per_H a multiple
+       of 16.  Two kernels on `stream`: a preprocessing kernel that leaves
+       each channel group's preconditioned G~, border c~, D and tau in the
+       workspace, and a solve kernel that keeps L~ in registers (one wave
+       per 16 vectors of a channel).  Workspace: taser_workspace_size()
+       bytes.
+     per-vector path: every other request with N - 1 <= 64 and U <= 32,
+       coherent (any y_per_H) or JED, BPSK or QPSK.  One kernel, one wave
+       per vector; it needs no workspace (taser_workspace_size() gives 0 and
+       ws may be NULL).
+   Other requests (U > 32 or N - 1 > 64) return TASER_ERR_UNSUPPORTED: use
+   taser_build_T / taser_solve / taser_detect, which cover N <= TASER_MAX_N.
    Same inputs as taser_build_T; tau_in [V] is read when tau_mode == GIVEN
    (else may be NULL).  ws: device buffer of at least
    taser_workspace_size() bytes owned by the caller (contents on entry are
    ignored; calls that share a workspace must not overlap).
    Outputs: sbar int8 [V][N-1]; margin float32 [V][N-1] or NULL; status [V];
-   L_out [V][N(N+1)/2] float32 or NULL (written only when non-NULL).
-   Supported: coherent QPSK with U = 16 (N = 33) and y_per_H a multiple of 16
-   (a wave detects the 16 vectors of one channel); other requests return
-   TASER_ERR_UNSUPPORTED (use the staged calls). */
+   L_out [V][N(N+1)/2] float32 or NULL (written only when non-NULL). */
 taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
                          const void* s0, const float* tau_in, int8_t* sbar, float* margin,
                          int32_t* status, float* L_out, void* ws, size_t ws_bytes,
@@ -280,7 +296,9 @@ taser_status_t taser_unfolded_forward(const taser_unfolded_t* u, const void* Tt,
 
 /* Backward: given dL [V][N(N+1)/2] = dLoss/dL_out, writes
    dalpha [t_max] = dLoss/dalpha_t summed over the batch (deterministic:
-   fixed-order reduction over vectors).  ws: taser_unfolded_sizes() bytes. */
+   fixed-order reduction over vectors).  ws: taser_unfolded_sizes() bytes.
+   An empty batch (V = 0) writes dalpha = 0 and needs only dalpha (the other
+   pointers may be NULL). */
 taser_status_t taser_unfolded_backward(const taser_unfolded_t* u, const void* Tt, const void* D,
                                        const void* lam, const void* alpha_t, const void* L_ckpt,
                                        const void* dL, void* dalpha, void* ws, size_t ws_bytes,

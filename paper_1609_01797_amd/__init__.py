@@ -74,6 +74,8 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     D = ctypes.POINTER(Desc)
     lib.taser_abi_version.restype = ctypes.c_int
+    lib.taser_debug_inject_device_error.restype = ctypes.c_int
+    lib.taser_debug_inject_device_error.argtypes = [ctypes.c_int32]
     lib.taser_status_string.restype = ctypes.c_char_p
     lib.taser_status_string.argtypes = [ctypes.c_int]
     lib.taser_problem_size.restype = ctypes.c_int
@@ -117,6 +119,12 @@ def load():
     lib.taser_unfolded_backward.argtypes = [U, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     _lib = lib
     return lib
+
+
+def inject_device_error(count: int) -> None:
+    """Testing aid: the next ``count`` launching calls fail with
+    TASER_ERR_DEVICE before they launch (``taser_debug_inject_device_error``)."""
+    _raise(load().taser_debug_inject_device_error(int(count)))
 
 
 def problem_size(U: int, mod: int) -> int:

@@ -28,8 +28,12 @@ def _arch():
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
-def cache_key(bucket, prec, t_max):
-    return f"{_arch()}|mixed|b{bucket}|p{prec}|t{t_max}"
+def cache_key(bucket, prec, t_max, num_vectors):
+    """Key of a tuned grid: architecture, bucket, precision, t_max and the
+    batch size class (log2 of the vector count: the best persistent grid
+    depends on how many vectors each bucket holds)."""
+    size_class = max(int(num_vectors), 1).bit_length()
+    return f"{_arch()}|mixed|b{bucket}|p{prec}|t{t_max}|v2^{size_class}"
 
 
 def load_cache(path=DEFAULT_CACHE):
@@ -49,13 +53,15 @@ def save_cache(cache, path=DEFAULT_CACHE):
         os.replace(tmp, path)
 
 
-def cached_blocks(prec, t_max, path=DEFAULT_CACHE):
+def cached_blocks(prec, t_max, num_vectors, path=DEFAULT_CACHE):
     """Tuned grid per bucket from the cache (0 = library default)."""
     cache = load_cache(path)
-    return [int(cache.get(cache_key(b, prec, t_max), {}).get("blocks", 0)) for b in range(3)]
+    return [int(cache.get(cache_key(b, prec, t_max, num_vectors), {}).get("blocks", 0))
+            for b in range(3)]
 
 
 def _time_call(fn, reps=5):
+    """Mean milliseconds of ``reps`` back-to-back calls (after one warm-up)."""
     import torch
     fn()
     torch.cuda.synchronize()
@@ -68,31 +74,67 @@ def _time_call(fn, reps=5):
     return a.elapsed_time(b) / reps
 
 
-def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=5, sweeps=1):
-    """Tune the per-bucket persistent grid of ``run_mixed(desc, *args)`` and
-    store it.  Returns (best blocks, best ms, default ms, trace)."""
+def _stats(ms):
+    import numpy as np
+    ms = np.asarray(ms, dtype=float)
+    return {"median_ms": float(np.median(ms)), "p10_ms": float(np.percentile(ms, 10)),
+            "p90_ms": float(np.percentile(ms, 90)), "samples": int(ms.size)}
+
+
+def compare(fn_a, fn_b, rounds=15, reps=3):
+    """Time two configurations interleaved (a, b, a, b, ...) so that drift of
+    the device clock or of other load affects both alike; returns the
+    statistics of each (median, p10, p90 of ``rounds`` timings)."""
+    ta, tb = [], []
+    for _ in range(rounds):
+        ta.append(_time_call(fn_a, reps))
+        tb.append(_time_call(fn_b, reps))
+    return _stats(ta), _stats(tb)
+
+
+def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sweeps=1, rounds=15):
+    """Tune the per-bucket grid of ``run_mixed(desc, *args)`` and store it.
+
+    Coordinate descent over the buckets with short timings proposes a
+    winner (a candidate equal to the current best is not timed again).  The
+    winner and the default are then timed interleaved over ``rounds``
+    rounds; the winner is adopted only if its median beats the default's
+    p10 (faster than the default's spread), otherwise the default is kept.
+    Returns (blocks, {"default": stats, "tuned": stats, "adopted": bool,
+    "proposed": blocks}, trace)."""
     import paper_1609_01797_amd as taser
     out = {}
-    ws = None
-    best = [0, 0, 0]
 
     def call(blocks):
-        return lambda: taser.run_mixed(desc, *args, blocks=blocks, out=out, ws=ws)
+        return lambda: taser.run_mixed(desc, *args, blocks=blocks, out=out)
 
-    default_ms = _time_call(call([0, 0, 0]), reps)
-    best_ms = default_ms
-    trace = [{"blocks": [0, 0, 0], "ms": default_ms}]
+    best = [0, 0, 0]
+    best_ms = _time_call(call(best), reps)
+    trace = [{"blocks": list(best), "ms": best_ms}]
     for _ in range(sweeps):
         for b in range(3):
             for c in candidates:
+                if c == best[b]:
+                    continue
                 trial = list(best)
                 trial[b] = c
                 ms = _time_call(call(trial), reps)
                 trace.append({"blocks": trial, "ms": ms})
                 if ms < best_ms:
                     best_ms, best = ms, trial
+    default = [0, 0, 0]
+    if best == default:
+        st, _ = compare(call(default), call(default), rounds=max(rounds // 3, 3), reps=reps)
+        report = {"default": st, "tuned": st, "adopted": False, "proposed": default}
+    else:
+        st_d, st_t = compare(call(default), call(best), rounds=rounds, reps=reps)
+        adopted = st_t["median_ms"] < st_d["p10_ms"]
+        report = {"default": st_d, "tuned": st_t, "adopted": adopted, "proposed": list(best)}
+        if not adopted:
+            best = default
     cache = load_cache(path)
     for b in range(3):
-        cache[cache_key(b, desc.prec, desc.t_max)] = {"blocks": best[b], "ms": best_ms}
+        cache[cache_key(b, desc.prec, desc.t_max, desc.num_vectors)] = {
+            "blocks": best[b], "median_ms": report["tuned" if report["adopted"] else "default"]["median_ms"]}
     save_cache(cache, path)
-    return best, best_ms, default_ms, trace
+    return best, report, trace

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <stdlib.h>
 
+#include <atomic>
+
 #include "taser_internal.h"
 
 using namespace taser;
@@ -42,11 +44,38 @@ StagedArgs staged_args(const taser_desc_t* d) {
   return a;
 }
 
+
+// Host-side fault injection (taser_debug_inject_device_error): the number of
+// upcoming launching calls that fail with TASER_ERR_DEVICE before they launch.
+std::atomic<int> g_inject{0};
+
+bool injected_device_error() {
+  int n = g_inject.load(std::memory_order_relaxed);
+  while (n > 0)
+    if (g_inject.compare_exchange_weak(n, n - 1, std::memory_order_relaxed)) return true;
+  return false;
+}
+
+// Every entry point that launches device work ends here: an injected fault,
+// or a failed launch (the launchers return hipGetLastError()), is
+// TASER_ERR_DEVICE.
+template <typename F>
+taser_status_t launch_status(F&& launch) {
+  if (injected_device_error()) return TASER_ERR_DEVICE;
+  return launch() == hipSuccess ? TASER_OK : TASER_ERR_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
 
 int taser_abi_version(void) { return TASER_ABI_VERSION; }
+
+taser_status_t taser_debug_inject_device_error(int32_t count) {
+  if (count < 0) return TASER_ERR_ARG;
+  g_inject.store(count, std::memory_order_relaxed);
+  return TASER_OK;
+}
 
 const char* taser_status_string(int status) {
   switch (status) {
@@ -85,8 +114,7 @@ taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void
   a.y = static_cast<const float2*>(y);
   a.s0 = static_cast<const float2*>(s0);
   a.Tt = Tt; a.D = D; a.lam = lam; a.tau = tau; a.status = status;
-  return launch_build_T(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
-                                                                          : TASER_ERR_DEVICE;
+  return launch_status([&] { return launch_build_T(a, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
@@ -97,9 +125,9 @@ taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const floa
   StagedArgs a = staged_args(desc);
   if (a.V == 0) return TASER_OK;
   if (!Tt || !D || !tau || !L || !status) return TASER_ERR_ARG;
-  return launch_solve(a, Tt, D, tau, L, status, static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_solve(a, Tt, D, tau, L, status, static_cast<hipStream_t>(stream));
+  });
 }
 
 taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const float* D,
@@ -109,10 +137,10 @@ taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const floa
   const int N = taser_problem_size(desc->U, desc->mod);
   if (desc->num_vectors == 0) return TASER_OK;
   if (!L || !D || !sbar) return TASER_ERR_ARG;
-  return launch_detect(desc->num_vectors, N, L, D, sbar, margin,
-                       static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_detect(desc->num_vectors, N, L, D, sbar, margin,
+                         static_cast<hipStream_t>(stream));
+  });
 }
 
 taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const void* s0,
@@ -122,10 +150,10 @@ taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const 
   if (desc->mode != TASER_JED) return TASER_ERR_ARG;
   if (desc->num_vectors == 0) return TASER_OK;
   if (!Y || !s0 || !sbar || !h) return TASER_ERR_ARG;
-  return launch_jed_channel(desc->num_vectors, desc->B, desc->U, desc->mod == TASER_QPSK, Y, s0,
-                            sbar, h, static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_jed_channel(desc->num_vectors, desc->B, desc->U, desc->mod == TASER_QPSK, Y, s0,
+                              sbar, h, static_cast<hipStream_t>(stream));
+  });
 }
 
 static taser_status_t fused_args(const taser_desc_t* desc, FusedArgs* a) {
@@ -149,27 +177,35 @@ taser_status_t taser_workspace_size(const taser_desc_t* desc, size_t* bytes) {
   return TASER_OK;
 }
 
-taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y, const void* s0,
-                         const float* tau_in, int8_t* sbar, float* margin, int32_t* status,
-                         float* L_out, void* ws, size_t ws_bytes, void* stream) {
-  FusedArgs a;
-  taser_status_t st = fused_args(desc, &a);
-  if (st != TASER_OK) return st;
-  if (a.V == 0) return TASER_OK;
+// Argument checks and argument block of taser_run (everything but the
+// workspace).
+static taser_status_t run_args(const taser_desc_t* desc, const void* H, const void* y,
+                               const void* s0, const float* tau_in, int8_t* sbar, float* margin,
+                               int32_t* status, float* L_out, FusedArgs* a) {
+  taser_status_t st = fused_args(desc, a);
+  if (st != TASER_OK || a->V == 0) return st;
   const bool jed = desc->mode == TASER_JED;
   if (!y || !sbar || !status) return TASER_ERR_ARG;
   if (!jed && !H) return TASER_ERR_ARG;
   if (jed && !s0) return TASER_ERR_ARG;
   if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
+  a->H = static_cast<const float2*>(H);
+  a->y = static_cast<const float2*>(y);
+  a->s0 = static_cast<const float2*>(s0);
+  a->tau_in = tau_in; a->sbar = sbar; a->margin = margin; a->status = status; a->L_out = L_out;
+  return TASER_OK;
+}
+
+taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y, const void* s0,
+                         const float* tau_in, int8_t* sbar, float* margin, int32_t* status,
+                         float* L_out, void* ws, size_t ws_bytes, void* stream) {
+  FusedArgs a;
+  taser_status_t st = run_args(desc, H, y, s0, tau_in, sbar, margin, status, L_out, &a);
+  if (st != TASER_OK || a.V == 0) return st;
   const size_t need = fused_workspace_bytes(a);
   if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
-  a.H = static_cast<const float2*>(H);
-  a.y = static_cast<const float2*>(y);
-  a.s0 = static_cast<const float2*>(s0);
-  a.tau_in = tau_in; a.sbar = sbar; a.margin = margin; a.status = status; a.L_out = L_out;
   a.ws = static_cast<float*>(ws);
-  return launch_fused(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
-                                                                        : TASER_ERR_DEVICE;
+  return launch_status([&] { return launch_fused(a, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const void* y,
@@ -192,8 +228,7 @@ taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const voi
   a.s0 = static_cast<const float2*>(s0);
   a.tau_in = tau_in; a.status = status;
   a.ws = static_cast<float*>(ws);
-  return launch_fused_prep(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
-                                                                             : TASER_ERR_DEVICE;
+  return launch_status([&] { return launch_fused_prep(a, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* margin,
@@ -209,8 +244,7 @@ taser_status_t taser_run_solve(const taser_desc_t* desc, int8_t* sbar, float* ma
   if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
   a.sbar = sbar; a.margin = margin; a.status = status; a.L_out = L_out;
   a.ws = static_cast<float*>(ws);
-  return launch_fused_solve(a, static_cast<hipStream_t>(stream)) == hipSuccess ? TASER_OK
-                                                                              : TASER_ERR_DEVICE;
+  return launch_status([&] { return launch_fused_solve(a, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws_bytes,
@@ -224,18 +258,16 @@ taser_status_t taser_run_tau(const taser_desc_t* desc, const void* ws, size_t ws
   const size_t need = fused_workspace_bytes(a);
   if (!ws || ws_bytes < need) return TASER_ERR_WORKSPACE;
   a.ws = static_cast<float*>(const_cast<void*>(ws));
-  return launch_fused_tau(a, tau, static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] { return launch_fused_tau(a, tau, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_calibrate(int32_t kind, int32_t iters, float* out, double* flops,
                                void* stream) {
   if (kind < 0 || kind > 2 || iters < 1 || iters > (1 << 16) || !out || !flops)
     return TASER_ERR_ARG;
-  return launch_calibrate(kind, iters, out, flops, static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_calibrate(kind, iters, out, flops, static_cast<hipStream_t>(stream));
+  });
 }
 
 int32_t taser_calibrate_elements(void) { return calib_elements(); }
@@ -288,10 +320,9 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, cons
   m.Bv = Bv; m.Uv = Uv; m.modv = modv; m.H_off = H_off; m.y_off = y_off; m.stride = stride;
   m.count = static_cast<int32_t*>(ws);
   m.list = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
-  return launch_mixed(a, m, launch ? launch->blocks : nullptr, static_cast<hipStream_t>(stream)) ==
-                 hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_mixed(a, m, launch ? launch->blocks : nullptr, static_cast<hipStream_t>(stream));
+  });
 }
 
 static taser_status_t unf_check(const taser_unfolded_t* u) {
@@ -327,10 +358,10 @@ taser_status_t taser_unfolded_forward(const taser_unfolded_t* u, const void* Tt,
   if (u->num_vectors == 0) return TASER_OK;
   if (!Tt || !D || !lam || !alpha_t || !L_ckpt || !L_out) return TASER_ERR_ARG;
   UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
-  return launch_unfolded_forward(a, Tt, D, lam, alpha_t, L_ckpt, L_out,
-                                 static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  return launch_status([&] {
+    return launch_unfolded_forward(a, Tt, D, lam, alpha_t, L_ckpt, L_out,
+                                   static_cast<hipStream_t>(stream));
+  });
 }
 
 taser_status_t taser_unfolded_backward(const taser_unfolded_t* u, const void* Tt, const void* D,
@@ -339,15 +370,16 @@ taser_status_t taser_unfolded_backward(const taser_unfolded_t* u, const void* Tt
                                        void* stream) {
   taser_status_t st = unf_check(u);
   if (st != TASER_OK) return st;
-  if (!Tt || !D || !lam || !alpha_t || !L_ckpt || !dL || !dalpha) return TASER_ERR_ARG;
+  if (!dalpha) return TASER_ERR_ARG;
+  if (u->num_vectors > 0 && (!Tt || !D || !lam || !alpha_t || !L_ckpt || !dL)) return TASER_ERR_ARG;
   UnfoldedArgs a{u->num_vectors, u->N, u->t_max, u->real, u->ckpt_every, u->flags};
   const size_t need = unfolded_workspace_bytes(a);
   if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
-  if (u->num_vectors == 0) return TASER_OK;
-  return launch_unfolded_backward(a, Tt, D, lam, alpha_t, L_ckpt, dL, dalpha, ws,
-                                  static_cast<hipStream_t>(stream)) == hipSuccess
-             ? TASER_OK
-             : TASER_ERR_DEVICE;
+  // an empty batch still writes dalpha (zeros: the sum over no vectors)
+  return launch_status([&] {
+    return launch_unfolded_backward(a, Tt, D, lam, alpha_t, L_ckpt, dL, dalpha, ws,
+                                    static_cast<hipStream_t>(stream));
+  });
 }
 
 }  // extern "C"

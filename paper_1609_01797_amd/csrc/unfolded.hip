@@ -56,7 +56,8 @@ template <typename Real>
 hipError_t bwd(const UnfoldedArgs& a, const void* Tt, const void* D, const void* lam,
                const void* alpha, const void* ckpt, const void* dL, void* dalpha, void* ws,
                hipStream_t s) {
-  hipError_t e = dispatch(a.N, [&](auto np) {
+  // an empty batch launches only the reduction, which writes dalpha = 0
+  hipError_t e = a.V == 0 ? hipSuccess : dispatch(a.N, [&](auto np) {
     constexpr int NP = decltype(np)::value;
     if constexpr (sizeof(Real) == 4 && NP <= 40) {
       if (unfolded_vectors_per_wave(a) == 2)

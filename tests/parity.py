@@ -36,3 +36,24 @@ def assert_decisions(sbar_gpu, sbar_ref, margin_ref, tol=MARGIN_TOL):
     bad = diff & (np.abs(margin_ref) >= tol)
     assert not bad.any(), f"{int(bad.sum())} decisions differ with |margin| >= {tol}"
     return int(diff.sum())
+
+
+def assert_16bit_low_snr(err, u, alpha):
+    """Bound on the per-vector relative L~ error of the 16-bit product paths
+    at low SNR (err: per-vector ||L~_gpu - L~_64||_F / ||L~_64||_F, u: unit
+    roundoff of the operand format).
+
+    alpha <= 1/2: the objective descends at every step (the sufficient-
+    decrease reading of Proposition 1), the trajectory is well conditioned
+    and every vector stays within the 2.5 u of the higher-SNR tests.
+    alpha > 1/2: descent is not guaranteed, and the prox amplifies a
+    perturbation of V by D_kk / ||V_:,k|| when a column of V nearly cancels,
+    so a few trajectories depart; the bound is then on quantiles: median
+    within u, 99 % of the vectors within 2.5 u and at most 1 % above it."""
+    err = np.asarray(err)
+    if alpha <= 0.5:
+        assert err.max() <= 2.5 * u, f"max {err.max() / u:.2f} u"
+        return
+    assert np.median(err) <= u, f"median {np.median(err) / u:.2f} u"
+    assert np.quantile(err, 0.99) <= 2.5 * u, f"p99 {np.quantile(err, 0.99) / u:.2f} u"
+    assert np.mean(err > 2.5 * u) <= 0.01, f"{np.mean(err > 2.5 * u) * 100:.2f} % above 2.5 u"

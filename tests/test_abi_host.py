@@ -222,3 +222,69 @@ def test_jed_channel_rejects_bad_arguments():
     assert lib.taser_jed_channel(ctypes.byref(jed), one, one, one, None, None) == taser.ERR_ARG
     empty = taser.make_desc(0, 16, 16, taser.QPSK, mode=taser.JED)
     assert lib.taser_jed_channel(ctypes.byref(empty), None, None, None, None, None) == taser.OK
+
+
+def test_device_error_path_through_fault_injection():
+    """TASER_ERR_DEVICE: with the host-side injection switch armed, every
+    entry point that launches device work returns TASER_ERR_DEVICE after its
+    argument checks and before launching (so this runs without a GPU); an
+    argument error still takes precedence and leaves the injection armed."""
+    lib = taser.load()
+    z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)   # never dereferenced
+    B_ = ctypes.byref
+    grp = taser.make_desc(64, 128, 16, taser.QPSK, y_per_H=16, t_max=10)
+    vec = taser.make_desc(64, 32, 8, taser.QPSK, t_max=10)
+    jed = taser.make_desc(8, 16, 16, taser.QPSK, mode=taser.JED, t_max=20)
+    mixed = taser.make_desc(10, 1, 1, taser.QPSK, t_max=10)
+    launch = taser.MixedLaunch()
+    fl = ctypes.c_double(0.0)
+    u = taser.UnfoldedDesc(4, 9, 5, taser.REAL_F32, 2, 0)
+    calls = {
+        "taser_build_T": lambda: lib.taser_build_T(B_(vec), one, one, z, one, one, one, one, one, z),
+        "taser_solve": lambda: lib.taser_solve(B_(vec), one, one, one, one, one, z),
+        "taser_detect": lambda: lib.taser_detect(B_(vec), one, one, one, one, z),
+        "taser_jed_channel": lambda: lib.taser_jed_channel(B_(jed), one, one, one, one, z),
+        "taser_run (group)": lambda: lib.taser_run(B_(grp), one, one, z, z, one, z, one, z, one, 1 << 20, z),
+        "taser_run (per-vector)": lambda: lib.taser_run(B_(vec), one, one, z, z, one, z, one, z, z, 0, z),
+        "taser_run_prep": lambda: lib.taser_run_prep(B_(grp), one, one, z, z, one, one, 1 << 20, z),
+        "taser_run_solve": lambda: lib.taser_run_solve(B_(grp), one, z, one, z, one, 1 << 20, z),
+        "taser_run_tau": lambda: lib.taser_run_tau(B_(grp), one, 1 << 20, one, z),
+        "taser_calibrate": lambda: lib.taser_calibrate(0, 10, one, B_(fl), z),
+        "taser_run_mixed": lambda: lib.taser_run_mixed(B_(mixed), *([one] * 7), z, one, z, 64, one, B_(launch),
+                                                       one, 1 << 20, z),
+        "taser_unfolded_forward": lambda: lib.taser_unfolded_forward(B_(u), one, one, one, one, one, one, z),
+        "taser_unfolded_backward": lambda: lib.taser_unfolded_backward(B_(u), one, one, one, one, one, one, one,
+                                                                       one, 1 << 20, z),
+    }
+    try:
+        for name, call in calls.items():
+            taser.inject_device_error(1)
+            assert call() == taser.ERR_DEVICE, name
+        # argument errors come first and do not consume the injection
+        taser.inject_device_error(1)
+        bad = taser.make_desc(64, 32, 8, 5)
+        assert lib.taser_run(B_(bad), one, one, z, z, one, z, one, z, z, 0, z) == taser.ERR_ARG
+        assert lib.taser_calibrate(9, 10, one, B_(fl), z) == taser.ERR_ARG
+        assert calls["taser_detect"]() == taser.ERR_DEVICE
+        assert lib.taser_debug_inject_device_error(-1) == taser.ERR_ARG
+        assert b"TASER_ERR_DEVICE" in lib.taser_status_string(taser.ERR_DEVICE)
+        with pytest.raises(taser.TaserError):
+            taser.inject_device_error(-2)
+    finally:
+        taser.inject_device_error(0)
+
+
+def test_workspace_size_per_vector_descriptors():
+    """The per-vector path (own channel, JED, any size with N - 1 <= 64 and
+    U <= 32) needs no workspace; the group path needs 1,472 floats per 16
+    vectors."""
+    lib = taser.load()
+    n = ctypes.c_size_t(123)
+    for d in (taser.make_desc(100, 64, 16, taser.QPSK), taser.make_desc(64, 128, 16, taser.QPSK, y_per_H=8),
+              taser.make_desc(32, 16, 16, taser.QPSK, mode=taser.JED), taser.make_desc(7, 256, 32, taser.QPSK),
+              taser.make_desc(9, 64, 8, taser.BPSK)):
+        n.value = 123
+        assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK and n.value == 0
+    d = taser.make_desc(48, 40, 16, taser.QPSK, y_per_H=16)
+    assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
+    assert n.value == 3 * 1472 * 4

@@ -216,6 +216,27 @@ def test_fused_16bit_products(gpu_lib, prec, snr):
     np.testing.assert_array_equal(g["status"], ref["status"])
 
 
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("snr", [-4.0, -2.0])
+@pytest.mark.parametrize("alpha", [0.5, 0.9])
+def test_fused_16bit_products_low_snr(gpu_lib, prec, snr, alpha):
+    """The low end of the benchmark's SNR sweep, 4,096 vectors, the oracle's
+    tau: decisions equal wherever the oracle's |margin| >= 10 u, and the L~
+    error bound of assert_16bit_low_snr (per vector for alpha <= 1/2, on
+    quantiles for the benchmark's alpha = 0.9)."""
+    from parity import assert_16bit_low_snr, rel_frobenius
+    d = sim.gen_mimo(B, U, oracle.QPSK, 256, YPH, snr,
+                     sim.seed_for(2, snr_index=400 + int(snr) + int(10 * alpha), shard=prec))
+    ref = _group_oracle(d, alpha, 10)
+    desc = gpu_lib.make_desc(4096, B, U, oracle.QPSK, prec=prec, tau_mode=gpu_lib.TAU_GIVEN, y_per_H=YPH,
+                             t_max=10)
+    g = fused(gpu_lib, desc, d["H"], d["y"], tau=ref["tau"].astype(np.float32))
+    u = PREC_TOL[prec][1] / 10
+    assert_16bit_low_snr(rel_frobenius(unpack_lower(g["L"], N), ref["L"]), u, alpha)
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=10 * u)
+    np.testing.assert_array_equal(g["status"], ref["status"])
+
+
 def test_fused_prep_then_solve_equals_run(gpu_lib):
     """taser_run_prep + taser_run_solve give exactly what taser_run gives, and
     one prep can feed solves of different product precisions."""

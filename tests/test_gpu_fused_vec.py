@@ -104,6 +104,34 @@ def test_vec_jed_16bit(gpu_lib, prec):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=mtol)
 
 
+@pytest.mark.parametrize("prec", [1, 2], ids=["bf16", "fp16"])
+@pytest.mark.parametrize("snr", [-4.0, -2.0])
+@pytest.mark.parametrize("alpha", [0.5, 0.9])
+@pytest.mark.parametrize("kind", ["coherent64x16", "jed16x16"])
+def test_vec_16bit_products_low_snr(gpu_lib, prec, snr, alpha, kind):
+    """The per-vector kernel with 16-bit products at -4 and -2 dB (own
+    channel 64x16 QPSK, t_max = 10; JED 16 antennas x 16 + 1 slots,
+    t_max = 20), 2,048 vectors, the oracle's tau: decisions equal wherever
+    the oracle's |margin| >= 10 u, L~ within assert_16bit_low_snr's bound."""
+    from parity import assert_16bit_low_snr, rel_frobenius
+    seed = sim.seed_for(3 if kind == "coherent64x16" else 5, snr_index=400 + int(snr) + int(10 * alpha),
+                        shard=prec)
+    if kind == "jed16x16":
+        d = sim.gen_jed(16, 16, oracle.QPSK, 2048, snr, seed)
+        ref = oracle.detect_jed(d["Y"], d["s0"], oracle.QPSK, alpha=alpha, t_max=20)
+        desc = gpu_lib.make_desc(2048, 16, 16, oracle.QPSK, mode=gpu_lib.JED, prec=prec,
+                                 tau_mode=gpu_lib.TAU_GIVEN, t_max=20)
+        g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"], tau=ref["tau"].astype(np.float32))
+    else:
+        d = sim.gen_mimo(64, 16, oracle.QPSK, 2048, 1, snr, seed)
+        ref = oracle.detect_coherent(d["H"], d["y"], oracle.QPSK, alpha=alpha, t_max=10)
+        desc = gpu_lib.make_desc(2048, 64, 16, oracle.QPSK, prec=prec, tau_mode=gpu_lib.TAU_GIVEN, t_max=10)
+        g = run_fused(gpu_lib, desc, H=d["H"], y=d["y"], tau=ref["tau"].astype(np.float32))
+    u = PREC_TOL[prec][1] / 10
+    assert_16bit_low_snr(rel_frobenius(unpack_lower(g["L"], 33), ref["L"]), u, alpha)
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"], tol=10 * u)
+
+
 def _assert_jed_prox_invariants(Lp, Y, s0, tol=2e-5):
     """Properties of every block's final L~ (Section II-B, III-C,
     Algorithm 1): T = -A^T A with A = [Hbar, ybar], so D_kk = sqrt(|T_kk|)

@@ -153,6 +153,65 @@ def test_first_iteration_closed_form_and_matched_filter(mod):
     np.testing.assert_array_equal(sbar, np.where(mf_bar >= 0, 1, -1))
 
 
+@pytest.mark.parametrize("mod", [oracle.QPSK, oracle.BPSK])
+def test_first_iteration_margin_closed_form(mod):
+    """The margin of slice_decisions is the last row of L = L~ D^-1
+    (Section III-C, L~ = L D).  After one iteration from L~(0) = D
+    (Algorithm 1), column k of V(1) is D_kk (1 - 2 tau) on the diagonal
+    (T~_kk = 1) and -2 tau T_ik / D_kk below it, so, derived by hand from T
+    itself,  margin_k = V_Nk / ||V_:,k||
+             = -2 tau T_Nk / sqrt(D_kk^4 (1 - 2 tau)^2 + 4 tau^2 sum_{i>k} T_ik^2).
+    Dividing by D_NN, or not dividing at all, fails this."""
+    H, y, _ = _mimo(12, 3, mod, 40, 0.0, 43)
+    T = oracle.build_T_coherent(H, y, mod)
+    D, Tt, _ = oracle.precondition(T)
+    tau = 0.3 / oracle.spectral_norm(Tt)
+    N = T.shape[-1]
+    res = oracle.run_taser(T, tau=tau, t_max=1, pin_last=True)
+    below = np.tril(T, -1) ** 2                       # T_ik^2 for i > k
+    col_tail = below.sum(axis=1)                      # sum over i > k, per column k
+    Dk = np.sqrt(np.diagonal(T, axis1=1, axis2=2))
+    t = tau[:, None]
+    expected = -2 * t * T[:, N - 1, :N - 1] / np.sqrt(
+        Dk[:, :N - 1] ** 4 * (1 - 2 * t) ** 2 + 4 * t ** 2 * col_tail[:, :N - 1])
+    np.testing.assert_allclose(res["margin"], expected, rtol=1e-12, atol=1e-15)
+
+
+def test_margin_bounded_by_column_norm():
+    """Every column of L~ has norm D_kk after the prox (Section III-C), so
+    the last-row entry of L = L~ D^-1 lies in [-1, 1], at any SNR, step
+    factor and iteration count; a margin divided by the wrong D leaves it."""
+    worst = 0.0
+    for seed, (mod, U, snr, alpha, t_max) in enumerate([(oracle.QPSK, 4, -6.0, 0.9, 10),
+                                                         (oracle.QPSK, 8, 3.0, 0.5, 20),
+                                                         (oracle.BPSK, 6, 10.0, 0.99, 5)]):
+        H, y, _ = _mimo(10, U, mod, 200, snr, 300 + seed)
+        res = oracle.detect_coherent(H, y, mod, alpha=alpha, t_max=t_max)
+        worst = max(worst, float(np.abs(res["margin"]).max()))
+        # and at the largest margins the bound is reached only by a column
+        # whose whole norm sits in its last entry
+        assert np.all(np.abs(res["margin"]) <= 1.0 + 1e-12)
+    assert worst > 0.5
+
+
+def test_last_row_mse_hand_value():
+    """The unfolded loss (the mean squared error between the last row of
+    L = L~ D^-1 and the transmitted real symbols), on values worked by hand:
+    vector 0: L~ last row (1, -2) with D = (2, 4) gives (0.5, -0.5) against
+    s = (+1, -1): errors 0.25 and 0.25; vector 1: last row (-3, 0) with
+    D = (3, 5) gives (-1, 0) against (+1, +1): errors 4 and 1.  Mean over
+    the four entries: 5.5 / 4 = 1.375."""
+    import torch
+    from oracle.unfolded import last_row_mse
+    L = torch.zeros(2, 3, 3, dtype=torch.float64)
+    L[0, 2, :2] = torch.tensor([1.0, -2.0])
+    L[1, 2, :2] = torch.tensor([-3.0, 0.0])
+    L[:, 2, 2] = 7.0                                  # held last entry: not part of the loss
+    D = torch.tensor([[2.0, 4.0, 7.0], [3.0, 5.0, 7.0]], dtype=torch.float64)
+    s = torch.tensor([[1.0, -1.0], [1.0, 1.0]], dtype=torch.float64)
+    assert float(last_row_mse(L, D, s)) == 1.375
+
+
 # ---------------------------------------------------------------- P6: one user / one slot
 
 @pytest.mark.parametrize("t_max", [1, 2, 5, 20])
