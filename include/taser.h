@@ -195,6 +195,22 @@ taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
                          int32_t* status, float* L_out, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* taser_run without a workspace argument, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid allocation).  The group path keeps its per-group
+   state in a device array inside the library (TASER_STATIC_MAX_VECTORS
+   vectors, 23 MiB, held on each device the library runs on until the
+   process ends); the per-vector path needs no state.  Same arguments,
+   kernels and results as taser_run.  The call allocates and frees nothing.
+   Calls on one device share that array: calls that overlap on one device
+   (on different streams, or from several threads) race and must not be
+   issued.  Errors: those of taser_run; TASER_ERR_WORKSPACE for a group-path
+   request of more than TASER_STATIC_MAX_VECTORS vectors. */
+#define TASER_STATIC_MAX_VECTORS 65536
+taser_status_t taser_run_static(const taser_desc_t* desc, const void* H, const void* y,
+                                const void* s0, const float* tau_in, int8_t* sbar, float* margin,
+                                int32_t* status, float* L_out, void* stream);
+
 /* The two stages of taser_run, for callers that time or schedule them
    separately.  taser_run_prep: T assembly, Jacobi preconditioning and the
    step size (Section II, Section III-C), leaving each group's state in `ws`

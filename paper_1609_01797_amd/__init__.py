@@ -92,6 +92,8 @@ def load():
     lib.taser_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
     lib.taser_run.restype = ctypes.c_int
     lib.taser_run.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.taser_run_static.restype = ctypes.c_int
+    lib.taser_run_static.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     lib.taser_mixed_workspace_size.restype = ctypes.c_int
     lib.taser_mixed_workspace_size.argtypes = [D, ctypes.POINTER(ctypes.c_size_t)]
     lib.taser_run_mixed.restype = ctypes.c_int

@@ -177,8 +177,8 @@ taser_status_t taser_workspace_size(const taser_desc_t* desc, size_t* bytes) {
   return TASER_OK;
 }
 
-// Argument checks and argument block of taser_run (everything but the
-// workspace).
+// Argument checks and argument block of taser_run and taser_run_static
+// (everything but the workspace).
 static taser_status_t run_args(const taser_desc_t* desc, const void* H, const void* y,
                                const void* s0, const float* tau_in, int8_t* sbar, float* margin,
                                int32_t* status, float* L_out, FusedArgs* a) {
@@ -206,6 +206,25 @@ taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
   if (need > 0 && (!ws || ws_bytes < need)) return TASER_ERR_WORKSPACE;
   a.ws = static_cast<float*>(ws);
   return launch_status([&] { return launch_fused(a, static_cast<hipStream_t>(stream)); });
+}
+
+taser_status_t taser_run_static(const taser_desc_t* desc, const void* H, const void* y,
+                                const void* s0, const float* tau_in, int8_t* sbar, float* margin,
+                                int32_t* status, float* L_out, void* stream) {
+  FusedArgs a;
+  taser_status_t st = run_args(desc, H, y, s0, tau_in, sbar, margin, status, L_out, &a);
+  if (st != TASER_OK || a.V == 0) return st;
+  const size_t need = fused_workspace_bytes(a);
+  if (need > static_scratch_bytes()) return TASER_ERR_WORKSPACE;
+  return launch_status([&] {
+    if (need > 0) {
+      void* p = nullptr;
+      const hipError_t e = static_scratch(&p);
+      if (e != hipSuccess) return e;
+      a.ws = static_cast<float*>(p);
+    }
+    return launch_fused(a, static_cast<hipStream_t>(stream));
+  });
 }
 
 taser_status_t taser_run_prep(const taser_desc_t* desc, const void* H, const void* y,

@@ -50,6 +50,10 @@ bool fused_group_supported(const FusedArgs& a);  // 16 vectors share one channel
 int fused_vec_tiles(const FusedArgs& a);         // per-vector kernel tile count, 0 = no
 hipError_t launch_fused_vec(const FusedArgs& a, hipStream_t s);
 size_t fused_workspace_bytes(const FusedArgs& a);
+// File-scope device state of taser_run_static (run_static.hip): its size and
+// the current device's address of it.
+size_t static_scratch_bytes();
+hipError_t static_scratch(void** ptr);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s);

@@ -154,6 +154,7 @@ def test_fused_entry_points_accept_an_empty_batch():
     for mode, B, U, yph in ((taser.COHERENT, 128, 16, 16), (taser.COHERENT, 32, 8, 1), (taser.JED, 16, 16, 1)):
         d = taser.make_desc(0, B, U, taser.QPSK, mode=mode, y_per_H=yph, t_max=10)
         assert lib.taser_run(ctypes.byref(d), z, z, z, z, z, z, z, z, z, 0, z) == taser.OK
+        assert lib.taser_run_static(ctypes.byref(d), z, z, z, z, z, z, z, z, z) == taser.OK
     head = taser.make_desc(0, 128, 16, taser.QPSK, y_per_H=16, t_max=10)
     assert lib.taser_run_prep(ctypes.byref(head), z, z, z, z, z, z, 0, z) == taser.OK
     assert lib.taser_run_solve(ctypes.byref(head), z, z, z, z, z, 0, z) == taser.OK
@@ -246,6 +247,8 @@ def test_device_error_path_through_fault_injection():
         "taser_jed_channel": lambda: lib.taser_jed_channel(B_(jed), one, one, one, one, z),
         "taser_run (group)": lambda: lib.taser_run(B_(grp), one, one, z, z, one, z, one, z, one, 1 << 20, z),
         "taser_run (per-vector)": lambda: lib.taser_run(B_(vec), one, one, z, z, one, z, one, z, z, 0, z),
+        "taser_run_static (group)": lambda: lib.taser_run_static(B_(grp), one, one, z, z, one, z, one, z, z),
+        "taser_run_static (per-vector)": lambda: lib.taser_run_static(B_(vec), one, one, z, z, one, z, one, z, z),
         "taser_run_prep": lambda: lib.taser_run_prep(B_(grp), one, one, z, z, one, one, 1 << 20, z),
         "taser_run_solve": lambda: lib.taser_run_solve(B_(grp), one, z, one, z, one, 1 << 20, z),
         "taser_run_tau": lambda: lib.taser_run_tau(B_(grp), one, 1 << 20, one, z),
