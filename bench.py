@@ -210,11 +210,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ber", action="store_true", help="skip the SNR sweep")
     ap.add_argument("--workload", default="coherent128x16",
-                    choices=["coherent128x16", "jed16x16", "coherent32x8", "mixed", "unfolded64x16"],
+                    choices=["coherent128x16", "jed16x16", "coherent32x8", "mixed", "unfolded64x16",
+                             "fixed128x16"],
                     help="coherent128x16 (default, the headline), jed16x16 (joint channel "
                          "estimation and detection, 262,144 blocks), coherent32x8 (1,000 vectors), "
                          "mixed (100,000 vectors over six (B, U, modulation) classes in one call), "
-                         "unfolded64x16 (learned step sizes: training steps/s and BER vs depth)")
+                         "unfolded64x16 (learned step sizes: training steps/s and BER vs depth), "
+                         "fixed128x16 (14-bit fixed-point mode: VER gap vs FP64 and solve time)")
     ap.add_argument("--counters", action="store_true",
                     help="run each calibration kernel once and one headline step per product "
                          "precision, then exit (the launches a --pmc counter pass reads)")

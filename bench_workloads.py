@@ -311,6 +311,109 @@ def run_unfolded_workload(args):
                              "smallest_depth_matching_plain_t10": smallest_depth("plain_t10")}}
 
 
+def _ver_gap(snrs, ver_ref, ver, target):
+    """SNR gap (dB) between two error-rate curves where the reference crosses
+    ``target`` (log-linear interpolation); None when either is not bracketed."""
+    def cross(v):
+        for (s0, b0), (s1, b1) in zip(zip(snrs, v), zip(snrs[1:], v[1:])):
+            if b0 >= target > b1 and b1 > 0:
+                l0, l1, lt = np.log10(b0), np.log10(b1), np.log10(target)
+                return s0 + (s1 - s0) * (l0 - lt) / (l0 - l1)
+        return None
+    a, b = cross(ver_ref), cross(ver)
+    return None if a is None or b is None else b - a
+
+
+def _oracle_coherent_chunk(job):
+    lo, hi, H, y, y_per_H, mod, alpha, t_max = job
+    from threadpoolctl import threadpool_limits
+    import oracle
+    with threadpool_limits(1):
+        Hv = np.repeat(H[lo // y_per_H: hi // y_per_H], y_per_H, axis=0)
+        return lo, oracle.detect_coherent(Hv, y[lo:hi], mod, alpha=alpha, t_max=t_max)["sbar"]
+
+
+def run_fixed_workload(args):
+    """The 14-bit fixed-point mode (Section IV-C) on the 128x16 QPSK workload
+    (16 vectors per channel, t_max = 10, alpha of the headline): paired
+    vector and bit error rates of the FP64 oracle, the float32 GPU path and
+    the fixed-point GPU path (float32 preprocessing, then taser_solve with
+    TASER_PREC_FIXED14) over -2..4 dB, 16,384 vectors per point; the SNR gap
+    at 1 % VER (the paper's criterion for its < 0.2 dB claim, Section V-A)
+    and at BER 1e-3; and the fixed-point solve's time on the full 65,536-
+    vector batch."""
+    import multiprocessing as mp
+    import torch
+    import paper_1609_01797_amd as taser
+    B, U, mod, yph, t_max = 128, 16, 2, 16, 10
+    alpha = alpha_star("coherent128x16")
+    N = 2 * U + 1
+    V = 16384
+    snrs = [-2.0, -1.0, 0.0, 1.0, 2.0, 3.0, 4.0]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ver = {"fp64": [], "fp32": [], "fixed14": []}
+    ber = {"fp64": [], "fp32": [], "fixed14": []}
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    t_cpu = 0.0
+    with mp.get_context("fork").Pool(cores) as pool:
+        for i, snr in enumerate(snrs):
+            d = sim.gen_mimo(B, U, mod, V // yph, yph, snr, sim.seed_for(2, snr_index=200 + i))
+            truth = np.concatenate([d["s"].real, d["s"].imag], axis=1).astype(np.int8)
+            step = V // cores // yph * yph
+            jobs = [(lo, min(V, lo + step), d["H"], d["y"], yph, mod, alpha, t_max) for lo in range(0, V, step)]
+            t0 = time.perf_counter()
+            parts = sorted(pool.map(_oracle_coherent_chunk, jobs), key=lambda p: p[0])
+            t_cpu += time.perf_counter() - t0
+            sb64 = np.concatenate([p[1] for p in parts], axis=0)
+            H, y = torch.from_numpy(d["H"]).to(dev), torch.from_numpy(d["y"]).to(dev)
+            desc = taser.make_desc(V, B, U, mod, y_per_H=yph, t_max=t_max, alpha=alpha)
+            sb32 = taser.run(desc, H, y)["sbar"].cpu().numpy()
+            fdesc = taser.make_desc(V, B, U, mod, y_per_H=yph, t_max=t_max, alpha=alpha,
+                                    prec=taser.PREC_FIXED14)
+            bt = taser.build_T(fdesc, H, y)
+            Lf = taser.solve(fdesc, bt["Tt"], bt["D"], bt["tau"], bt["status"])
+            sbf, _ = taser.detect(fdesc, Lf, bt["D"], want_margin=False)
+            sbf = sbf.cpu().numpy()
+            for name, sb in (("fp64", sb64), ("fp32", sb32), ("fixed14", sbf)):
+                wrong = sb != truth
+                ver[name].append(float(np.mean(np.any(wrong, axis=1))))
+                ber[name].append(float(np.mean(wrong)))
+            del bt, Lf
+    # throughput of the fixed-point solve on the full batch (10 dB)
+    Vf = 65536
+    d = sim.gen_mimo(B, U, mod, Vf // yph, yph, 10.0, sim.seed_for(2, snr_index=20))
+    H, y = torch.from_numpy(d["H"]).to(dev), torch.from_numpy(d["y"]).to(dev)
+    fdesc = taser.make_desc(Vf, B, U, mod, y_per_H=yph, t_max=t_max, alpha=alpha, prec=taser.PREC_FIXED14)
+    bt = taser.build_T(fdesc, H, y)
+    words = taser.fixed_quantize(fdesc, bt["Tt"], bt["D"], bt["tau"])
+    ms_build = _time(lambda: taser.build_T(fdesc, H, y), args.steps, args.warmup, stream)
+    ms_quant = _time(lambda: taser.fixed_quantize(fdesc, bt["Tt"], bt["D"], bt["tau"]), args.steps,
+                     args.warmup, stream)
+    st = bt["status"].clone()
+    ms_solve = _time(lambda: taser.fixed_solve(fdesc, words["That"], words["D"], st), args.steps,
+                     args.warmup, stream)
+    macs = t_max * N * (N + 1) * (2 * N + 1) // 6
+    gaps = {name: {"at_ver_1e-2": _ver_gap(snrs, ver["fp64"], ver[name], 1e-2),
+                   "at_ber_1e-3": _ver_gap(snrs, ber["fp64"], ber[name], 1e-3)} for name in ("fp32", "fixed14")}
+    return {"metric": "fixed-point (14-bit, Section IV-C) VER gap vs FP64 @128x16 QPSK t_max=10",
+            "value": gaps["fixed14"]["at_ver_1e-2"], "unit": "dB", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "int14",
+            "data": "synthetic",
+            "config": {"workload": "fixed128x16", "B": B, "U": U, "modulation": "QPSK", "N": N,
+                       "vectors_per_snr": V, "y_per_H": yph, "t_max": t_max, "alpha": alpha,
+                       "snr_db": snrs, "formats": "L~/V 8 fraction bits, bottom row 7, L~_NN 5, "
+                                                 "T^ 12, scale 11, rsqrt table 2^11 x 13 bits"},
+            "accuracy": {"ver": ver, "ber": ber, "gap_db": gaps,
+                         "paper_claim": "< 0.2 dB at 1% VER (Section V-A, on 128x8, 64x16, 32x32 systems)"},
+            "paths": {"fixed14": {"vectors": Vf, "build_T_ms": ms_build, "quantize_ms": ms_quant,
+                                  "fixed_solve_ms": ms_solve, "solve_vectors_per_s": Vf / (ms_solve * 1e-3),
+                                  "int_macs_per_vector": macs}},
+            "cpu_baseline": {"value": V * len(snrs) / t_cpu, "unit": "vectors/s", "cores": cores,
+                             "kind": "oracle", "sample": f"{len(snrs)} SNR points x {V} vectors, FP64 oracle, "
+                             f"{cores} single-threaded worker processes"}}
+
+
 def run_counters(args):
     """One launch per product precision of a secondary workload, nothing
     else: the launches a rocprofv3 --pmc counter pass reads."""
@@ -345,6 +448,8 @@ def run_workload(args):
         return run_mixed_workload(args)
     if args.workload == "unfolded64x16":
         return run_unfolded_workload(args)
+    if args.workload == "fixed128x16":
+        return run_fixed_workload(args)
     if args.workload == "jed16x16":
         kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, alpha_star("jed16x16")
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0], 6.0, 16384

@@ -63,9 +63,12 @@ typedef enum {
 
 enum { TASER_BPSK = 1, TASER_QPSK = 2 };
 enum { TASER_COHERENT = 0, TASER_JED = 1 };
-/* Arithmetic of the L~ T~ products in the main loop.  Norms, rsqrt, the
-   preconditioner and the master copy of L~ are float32 in every mode. */
-enum { TASER_PREC_F32 = 0, TASER_PREC_BF16 = 1, TASER_PREC_F16 = 2 };
+/* Arithmetic of the main loop.  F32 / BF16 / F16 select the operands of the
+   L~ T~ products; norms, rsqrt, the preconditioner and the master copy of L~
+   are float32 in those modes.  FIXED14 runs the whole loop in the 14-bit
+   fixed-point arithmetic of the paper's hardware (Section IV-C; see
+   taser_fixed_solve) and is accepted by taser_solve only. */
+enum { TASER_PREC_F32 = 0, TASER_PREC_BF16 = 1, TASER_PREC_F16 = 2, TASER_PREC_FIXED14 = 3 };
 enum { TASER_TAU_SPECTRAL = 0,   /* tau = alpha / ||T~||_2 (Algorithm 1 inputs) */
        TASER_TAU_GIVEN = 1 };    /* tau[v] supplied by the caller */
 
@@ -140,10 +143,46 @@ taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void
    Inputs: Tt [V][N][N], D [V][N], tau [V] (float32), status [V] from
    taser_build_T (vectors flagged DEGENERATE or NONFINITE run no iterations
    and get L~ = D).  Output: L [V][N(N+1)/2] packed float32; status gains
-   TASER_VEC_ZERO_NORM / TASER_VEC_VNN_NONPOS bits.  desc->prec selects the
-   product arithmetic (only TASER_PREC_F32 in this entry point). */
+   TASER_VEC_ZERO_NORM / TASER_VEC_VNN_NONPOS bits.  desc->prec: TASER_PREC_F32,
+   or TASER_PREC_FIXED14 (N <= 64): T^ = 2 tau T~ and D are quantised as
+   taser_fixed_quantize does, the loop runs as taser_fixed_solve, and L holds
+   the exact real values of the resulting words (VNN_NONPOS is not
+   reported: the hardware has no element for V_NN).  Other precisions return
+   TASER_ERR_UNSUPPORTED. */
 taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
                            const float* tau, float* L, int32_t* status, void* stream);
+
+/* ---- Fixed-point mode (Section IV-C) ----------------------------------
+
+   Algorithm 1 in the 14-bit fixed-point arithmetic of the paper's systolic
+   array.  A word is a 14-bit two's complement integer w with value
+   w 2^-F; words saturate at [-8192, 8191].  Fraction bits F, as the paper
+   gives them: 8 for L~ and V in rows 1..N-1, 7 in row N (the bottom row of
+   the array), 5 for L~_NN (held constant at D_NN).  Readings where the
+   paper is silent: T^ = 2 tau T~ with 12 fraction bits, D_kk with 8 (D_NN
+   with 5); each V_ij is its exact sum of products rounded once (to nearest,
+   ties upwards); column norms are exact with 16 fraction bits; the inverse
+   square root comes from a 2^11-entry table of 14-bit words with 13
+   fraction bits (entry i: the integer nearest to 2^13/sqrt((i+1/2)/2^10)),
+   indexed by the top 11 bits of the squared norm after an even normalising
+   shift; the scale factor D_jj/||v_j|| has 11 fraction bits.  N <= 64;
+   larger problems return TASER_ERR_UNSUPPORTED.
+
+   taser_fixed_quantize: the preprocessing outputs of taser_build_T (Tt
+   [V][N][N], D [V][N], tau [V], float32) to words: That int16 [V][N][N],
+   Dq int16 [V][N].  2 tau T~ is formed as one float32 product.
+   taser_fixed_solve: L~(0) = D, t_max fixed-point iterations and slicing.
+   In: That, Dq (words), status [V] from taser_build_T (DEGENERATE or
+   NONFINITE vectors run no iterations).  Out: L int16 [V][N(N+1)/2] packed
+   rows of words (row N holds 7-bit words and the 5-bit L~_NN); sbar int8
+   [V][N-1] = sign(L~_Nk) with sign(0) = +1, or NULL; status gains
+   TASER_VEC_ZERO_NORM when a column of V was zero (reset to D_jj e_j).
+   All arrays are device memory owned by the caller; errors: those of
+   taser_check_desc, TASER_ERR_ARG (NULL pointers), TASER_ERR_UNSUPPORTED. */
+taser_status_t taser_fixed_quantize(const taser_desc_t* desc, const float* Tt, const float* D,
+                                    const float* tau, int16_t* That, int16_t* Dq, void* stream);
+taser_status_t taser_fixed_solve(const taser_desc_t* desc, const int16_t* That, const int16_t* Dq,
+                                 int16_t* L, int8_t* sbar, int32_t* status, void* stream);
 
 /* Algorithm 1 output: sbar_k = sign(L~_{N,k}) for k = 1..N-1 (sign(0) = +1),
    int8 sbar [V][N-1] in s~ order; margin [V][N-1] float32 = L~_{N,k}/D_kk

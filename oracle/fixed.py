@@ -127,13 +127,19 @@ def scale_factor(q, d):
     return out
 
 
-def fixed_inputs(Tt, D, tau):
+def fixed_inputs(Tt, D, tau, product_dtype=np.float64):
     """Quantise the preprocessing outputs (F2): T^ = 2 tau T~ with 12
-    fraction bits; D_kk with 8 (k < N) and D_NN with 5 fraction bits."""
+    fraction bits; D_kk with 8 (k < N) and D_NN with 5 fraction bits.
+    ``product_dtype`` is the precision in which 2 tau T~ is formed before
+    rounding to a word: float64 here, float32 to take the same decision as a
+    float32 preprocessing does (2 tau is exact in either; the product is
+    rounded once)."""
     Tt = np.asarray(Tt, dtype=np.float64)
     D = np.asarray(D, dtype=np.float64)
     tau = np.asarray(tau, dtype=np.float64)
-    That = quantize(2.0 * tau[..., None, None] * Tt, F_T)
+    two_tau = (2.0 * tau).astype(product_dtype)[..., None, None]
+    prod = (two_tau * Tt.astype(product_dtype)).astype(np.float64)
+    That = quantize(prod, F_T)
     d = quantize(D, F_L)
     d[..., -1] = quantize(D[..., -1], F_NN)
     return That, d

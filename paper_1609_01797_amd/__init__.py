@@ -15,7 +15,7 @@ import ctypes
 import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
-           "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16",
+           "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16", "PREC_FIXED14",
            "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "calibrate", "jed_channel", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
            "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
@@ -25,7 +25,7 @@ LIB_PATH = os.environ.get("TASER_LIB") or os.path.join(os.path.dirname(os.path.a
 
 BPSK, QPSK = 1, 2
 COHERENT, JED = 0, 1
-PREC_F32, PREC_BF16, PREC_F16 = 0, 1, 2
+PREC_F32, PREC_BF16, PREC_F16, PREC_FIXED14 = 0, 1, 2, 3
 TAU_SPECTRAL, TAU_GIVEN = 0, 1
 FLAG_LITERAL_LAST = 1
 VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS, VEC_UNSUPPORTED = 1, 2, 4, 8, 16
@@ -105,6 +105,10 @@ def load():
     lib.taser_run_solve.argtypes = [D, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.taser_run_tau.restype = ctypes.c_int
     lib.taser_run_tau.argtypes = [D, _P, ctypes.c_size_t, _P, _P]
+    lib.taser_fixed_quantize.restype = ctypes.c_int
+    lib.taser_fixed_quantize.argtypes = [D, _P, _P, _P, _P, _P, _P]
+    lib.taser_fixed_solve.restype = ctypes.c_int
+    lib.taser_fixed_solve.argtypes = [D, _P, _P, _P, _P, _P, _P]
     lib.taser_jed_channel.restype = ctypes.c_int
     lib.taser_jed_channel.argtypes = [D, _P, _P, _P, _P, _P]
     lib.taser_calibrate.restype = ctypes.c_int
@@ -243,6 +247,38 @@ def detect(desc: Desc, L, D, want_margin=True):
                           _stream(L.device))
     _raise(st)
     return sbar, margin
+
+
+def fixed_quantize(desc: Desc, Tt, D, tau):
+    """Preprocessing outputs (float32 Tt [V,N,N], D [V,N], tau [V]) to the
+    14-bit words of the fixed-point mode: dict That int16 [V,N,N], D int16
+    [V,N]."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    out = {"That": torch.empty((V, N, N), dtype=torch.int16, device=Tt.device),
+           "D": torch.empty((V, N), dtype=torch.int16, device=Tt.device)}
+    _raise(lib.taser_fixed_quantize(ctypes.byref(desc), _need(Tt, torch.float32, V * N * N, "Tt"),
+                                    _need(D, torch.float32, V * N, "D"), _need(tau, torch.float32, V, "tau"),
+                                    _need(out["That"], torch.int16, V * N * N, "That"),
+                                    _need(out["D"], torch.int16, V * N, "Dq"), _stream(Tt.device)))
+    return out
+
+
+def fixed_solve(desc: Desc, That, Dq, status):
+    """Fixed-point Algorithm 1 on words: dict L int16 [V, N(N+1)/2] (packed
+    words), sbar int8 [V, N-1], status (``status`` is updated in place)."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    out = {"L": torch.empty((V, N * (N + 1) // 2), dtype=torch.int16, device=That.device),
+           "sbar": torch.empty((V, N - 1), dtype=torch.int8, device=That.device), "status": status}
+    _raise(lib.taser_fixed_solve(ctypes.byref(desc), _need(That, torch.int16, V * N * N, "That"),
+                                 _need(Dq, torch.int16, V * N, "Dq"),
+                                 _need(out["L"], torch.int16, V * N * (N + 1) // 2, "L"),
+                                 _need(out["sbar"], torch.int8, V * (N - 1), "sbar"),
+                                 _need(status, torch.int32, V, "status"), _stream(That.device)))
+    return out
 
 
 def jed_channel(desc: Desc, Y, s0, sbar):

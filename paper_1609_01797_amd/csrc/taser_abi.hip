@@ -14,8 +14,7 @@ namespace {
 bool valid_enums(const taser_desc_t* d) {
   if (d->mod != TASER_BPSK && d->mod != TASER_QPSK) return false;
   if (d->mode != TASER_COHERENT && d->mode != TASER_JED) return false;
-  if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)
-    return false;
+  if (d->prec < TASER_PREC_F32 || d->prec > TASER_PREC_FIXED14) return false;
   if (d->tau_mode != TASER_TAU_SPECTRAL && d->tau_mode != TASER_TAU_GIVEN) return false;
   if (d->flags & ~TASER_FLAG_LITERAL_LAST) return false;
   return true;
@@ -117,14 +116,27 @@ taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void
   return launch_status([&] { return launch_build_T(a, static_cast<hipStream_t>(stream)); });
 }
 
+static FixedArgs fixed_args(const taser_desc_t* d) {
+  FixedArgs f{};
+  f.V = d->num_vectors; f.N = taser_problem_size(d->U, d->mod); f.t_max = d->t_max;
+  return f;
+}
+
 taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
                            const float* tau, float* L, int32_t* status, void* stream) {
   taser_status_t st = check(desc);
   if (st != TASER_OK) return st;
-  if (desc->prec != TASER_PREC_F32) return TASER_ERR_UNSUPPORTED;
+  if (desc->prec != TASER_PREC_F32 && desc->prec != TASER_PREC_FIXED14) return TASER_ERR_UNSUPPORTED;
+  if (desc->prec == TASER_PREC_FIXED14 && taser_problem_size(desc->U, desc->mod) > 64)
+    return TASER_ERR_UNSUPPORTED;
   StagedArgs a = staged_args(desc);
   if (a.V == 0) return TASER_OK;
   if (!Tt || !D || !tau || !L || !status) return TASER_ERR_ARG;
+  if (desc->prec == TASER_PREC_FIXED14) {
+    FixedArgs f = fixed_args(desc);
+    f.Tt = Tt; f.Df = D; f.tau = tau; f.Lf = L; f.status = status;
+    return launch_status([&] { return launch_fixed_solve(f, static_cast<hipStream_t>(stream)); });
+  }
   return launch_status([&] {
     return launch_solve(a, Tt, D, tau, L, status, static_cast<hipStream_t>(stream));
   });
@@ -141,6 +153,31 @@ taser_status_t taser_detect(const taser_desc_t* desc, const float* L, const floa
     return launch_detect(desc->num_vectors, N, L, D, sbar, margin,
                          static_cast<hipStream_t>(stream));
   });
+}
+
+taser_status_t taser_fixed_quantize(const taser_desc_t* desc, const float* Tt, const float* D,
+                                    const float* tau, int16_t* That, int16_t* Dq, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  if (taser_problem_size(desc->U, desc->mod) > 64) return TASER_ERR_UNSUPPORTED;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!Tt || !D || !tau || !That || !Dq) return TASER_ERR_ARG;
+  const FixedArgs f = fixed_args(desc);
+  return launch_status([&] {
+    return launch_fixed_quantize(f, Tt, D, tau, That, Dq, static_cast<hipStream_t>(stream));
+  });
+}
+
+taser_status_t taser_fixed_solve(const taser_desc_t* desc, const int16_t* That, const int16_t* Dq,
+                                 int16_t* L, int8_t* sbar, int32_t* status, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  if (taser_problem_size(desc->U, desc->mod) > 64) return TASER_ERR_UNSUPPORTED;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!That || !Dq || !L || !status) return TASER_ERR_ARG;
+  FixedArgs f = fixed_args(desc);
+  f.That = That; f.D = Dq; f.L = L; f.sbar = sbar; f.status = status;
+  return launch_status([&] { return launch_fixed_solve(f, static_cast<hipStream_t>(stream)); });
 }
 
 taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const void* s0,
@@ -164,7 +201,7 @@ static taser_status_t fused_args(const taser_desc_t* desc, FusedArgs* a) {
   a->N = taser_problem_size(desc->U, desc->mod);
   a->mod = desc->mod; a->mode = desc->mode; a->y_per_H = desc->y_per_H; a->t_max = desc->t_max;
   a->flags = desc->flags; a->tau_mode = desc->tau_mode; a->prec = desc->prec; a->alpha = desc->alpha;
-  if (!fused_supported(*a)) return TASER_ERR_UNSUPPORTED;
+  if (desc->prec == TASER_PREC_FIXED14 || !fused_supported(*a)) return TASER_ERR_UNSUPPORTED;
   return TASER_OK;
 }
 
@@ -293,13 +330,12 @@ int32_t taser_calibrate_elements(void) { return calib_elements(); }
 
 static taser_status_t mixed_check(const taser_desc_t* d) {
   if (!d) return TASER_ERR_ARG;
-  if (d->prec != TASER_PREC_F32 && d->prec != TASER_PREC_BF16 && d->prec != TASER_PREC_F16)
-    return TASER_ERR_ARG;
+  if (d->prec < TASER_PREC_F32 || d->prec > TASER_PREC_FIXED14) return TASER_ERR_ARG;
   if (d->tau_mode != TASER_TAU_SPECTRAL && d->tau_mode != TASER_TAU_GIVEN) return TASER_ERR_ARG;
   if (d->flags & ~TASER_FLAG_LITERAL_LAST) return TASER_ERR_ARG;
   if (d->t_max < 0 || d->t_max > 100000) return TASER_ERR_ARG;
   if (d->tau_mode == TASER_TAU_SPECTRAL && !(d->alpha > 0.f && d->alpha < 1.f)) return TASER_ERR_ARG;
-  if (d->mode != TASER_COHERENT) return TASER_ERR_UNSUPPORTED;
+  if (d->mode != TASER_COHERENT || d->prec == TASER_PREC_FIXED14) return TASER_ERR_UNSUPPORTED;
   if (d->num_vectors < 0 || d->num_vectors > TASER_MAX_VECTORS) return TASER_ERR_SHAPE;
   return TASER_OK;
 }

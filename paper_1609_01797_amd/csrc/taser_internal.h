@@ -63,6 +63,26 @@ hipError_t launch_jed_channel(int V, int B, int K, bool qpsk, const void* Y, con
                               const int8_t* sbar, void* h, hipStream_t s);
 hipError_t launch_calibrate(int kind, int iters, float* out, double* flops, hipStream_t s);
 
+// Fixed-point Algorithm 1 (Section IV-C), N <= 64.  Inputs: words That
+// [V][N][N] and D [V][N], or (Tt set) the float32 T~ [V][N][N], D [V][N] and
+// tau [V] quantised in the kernel.  Outputs: words L and / or real values Lf
+// [V][N(N+1)/2], decisions sbar [V][N-1] (or NULL), status [V] (in / out).
+struct FixedArgs {
+  int32_t V, N, t_max;
+  const int16_t* That;
+  const int16_t* D;
+  const float* Tt;
+  const float* Df;
+  const float* tau;
+  int16_t* L;
+  float* Lf;
+  int8_t* sbar;
+  int32_t* status;
+};
+hipError_t launch_fixed_quantize(const FixedArgs& a, const float* Tt, const float* D,
+                                 const float* tau, int16_t* That, int16_t* Dq, hipStream_t s);
+hipError_t launch_fixed_solve(const FixedArgs& a, hipStream_t s);
+
 // Mixed-size batches: per-vector sizes and offsets, and the bucket lists in
 // the workspace (count[kMixedBuckets] then kMixedBuckets lists of V indices).
 constexpr int kMixedBuckets = 3;

@@ -46,6 +46,7 @@ def _d(**kw):
     (dict(mod=3), taser.ERR_ARG),
     (dict(mode=2), taser.ERR_ARG),
     (dict(prec=9), taser.ERR_ARG),
+    (dict(prec=3), taser.OK),               # TASER_PREC_FIXED14 (taser_solve only)
     (dict(tau_mode=2), taser.ERR_ARG),
     (dict(flags=2), taser.ERR_ARG),
     (dict(t_max=-1), taser.ERR_ARG),
@@ -236,6 +237,7 @@ def test_device_error_path_through_fault_injection():
     grp = taser.make_desc(64, 128, 16, taser.QPSK, y_per_H=16, t_max=10)
     vec = taser.make_desc(64, 32, 8, taser.QPSK, t_max=10)
     jed = taser.make_desc(8, 16, 16, taser.QPSK, mode=taser.JED, t_max=20)
+    fx = taser.make_desc(64, 32, 8, taser.QPSK, t_max=10, prec=taser.PREC_FIXED14)
     mixed = taser.make_desc(10, 1, 1, taser.QPSK, t_max=10)
     launch = taser.MixedLaunch()
     fl = ctypes.c_double(0.0)
@@ -249,6 +251,9 @@ def test_device_error_path_through_fault_injection():
         "taser_run (per-vector)": lambda: lib.taser_run(B_(vec), one, one, z, z, one, z, one, z, z, 0, z),
         "taser_run_static (group)": lambda: lib.taser_run_static(B_(grp), one, one, z, z, one, z, one, z, z),
         "taser_run_static (per-vector)": lambda: lib.taser_run_static(B_(vec), one, one, z, z, one, z, one, z, z),
+        "taser_solve (fixed14)": lambda: lib.taser_solve(B_(fx), one, one, one, one, one, z),
+        "taser_fixed_quantize": lambda: lib.taser_fixed_quantize(B_(vec), one, one, one, one, one, z),
+        "taser_fixed_solve": lambda: lib.taser_fixed_solve(B_(vec), one, one, one, z, one, z),
         "taser_run_prep": lambda: lib.taser_run_prep(B_(grp), one, one, z, z, one, one, 1 << 20, z),
         "taser_run_solve": lambda: lib.taser_run_solve(B_(grp), one, z, one, z, one, 1 << 20, z),
         "taser_run_tau": lambda: lib.taser_run_tau(B_(grp), one, 1 << 20, one, z),
@@ -291,3 +296,29 @@ def test_workspace_size_per_vector_descriptors():
     d = taser.make_desc(48, 40, 16, taser.QPSK, y_per_H=16)
     assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
     assert n.value == 3 * 1472 * 4
+
+
+def test_fixed_point_entry_points_reject_before_any_launch():
+    """Fixed-point mode: N <= 64 only, NULL checks, FIXED14 unsupported by the
+    fused and mixed paths, empty batches are no-ops (no device work)."""
+    lib = taser.load()
+    z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)
+    big = taser.make_desc(4, 64, 40, taser.QPSK, t_max=10)           # N = 81
+    ok = taser.make_desc(4, 32, 8, taser.QPSK, t_max=10)
+    fx = taser.make_desc(64, 128, 16, taser.QPSK, y_per_H=16, t_max=10, prec=taser.PREC_FIXED14)
+    n = ctypes.c_size_t(0)
+    assert lib.taser_fixed_quantize(ctypes.byref(big), one, one, one, one, one, z) == taser.ERR_UNSUPPORTED
+    assert lib.taser_fixed_solve(ctypes.byref(big), one, one, one, z, one, z) == taser.ERR_UNSUPPORTED
+    assert lib.taser_fixed_quantize(ctypes.byref(ok), one, z, one, one, one, z) == taser.ERR_ARG
+    assert lib.taser_fixed_solve(ctypes.byref(ok), one, one, z, z, one, z) == taser.ERR_ARG
+    assert lib.taser_fixed_solve(ctypes.byref(ok), one, one, one, z, z, z) == taser.ERR_ARG
+    assert lib.taser_workspace_size(ctypes.byref(fx), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
+    assert lib.taser_run(ctypes.byref(fx), one, one, z, z, one, z, one, z, one, 1 << 20, z) == taser.ERR_UNSUPPORTED
+    assert lib.taser_mixed_workspace_size(ctypes.byref(fx), ctypes.byref(n)) == taser.ERR_UNSUPPORTED
+    bigfx = taser.make_desc(4, 64, 40, taser.QPSK, t_max=10, prec=taser.PREC_FIXED14)
+    assert lib.taser_solve(ctypes.byref(bigfx), one, one, one, one, one, z) == taser.ERR_UNSUPPORTED
+    bf = taser.make_desc(4, 32, 8, taser.QPSK, t_max=10, prec=taser.PREC_BF16)
+    assert lib.taser_solve(ctypes.byref(bf), one, one, one, one, one, z) == taser.ERR_UNSUPPORTED
+    empty = taser.make_desc(0, 32, 8, taser.QPSK, t_max=10)
+    assert lib.taser_fixed_quantize(ctypes.byref(empty), z, z, z, z, z, z) == taser.OK
+    assert lib.taser_fixed_solve(ctypes.byref(empty), z, z, z, z, z, z) == taser.OK
