@@ -68,6 +68,24 @@ __device__ __forceinline__ f4 mfma16(u2 a, u2 b, f4 c) {
                                                  __builtin_bit_cast(h4, b), c, 0, 0, 0);
 }
 
+// One 16x16x32 product: the K slots of two 16-column tiles side by side,
+// a = [a0, a1], b = [b0, b1] (the same K order in both operands).  On gfx950
+// it takes the cycles of one 16x16x16 product for twice the work.
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ __forceinline__ f4 mfma32(u2 a0, u2 a1, u2 b0, u2 b1, f4 c) {
+  const u4 a = {a0[0], a0[1], a1[0], a1[1]}, b = {b0[0], b0[1], b1[0], b1[1]};
+  if constexpr (P == TASER_PREC_BF16) {
+    typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a),
+                                                   __builtin_bit_cast(b8, b), c, 0, 0, 0);
+  } else {
+    typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a),
+                                                  __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+  }
+}
+
 // Sum over the four column quads (lanes n, n+16, n+32, n+48).
 __device__ __forceinline__ float sum_quads(float x) {
   const unsigned u = __float_as_uint(x);
@@ -86,6 +104,53 @@ __device__ __forceinline__ float sum_rows16(float x) {
   x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, false));
   x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, false));
   return x;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// One level of a transpose-reduction inside 16-lane rows: each lane swaps
+// half of its K values with its DPP partner (an involution of the row) and
+// keeps the half that `upper` selects, summed with the partner's copy.
+template <int K, int CTRL>
+__device__ __forceinline__ void halve_rows16(float* x, bool upper) {
+#pragma unroll
+  for (int a = 0; a < K / 2; ++a) {
+    const float keep = upper ? x[a + K / 2] : x[a];
+    const float send = upper ? x[a] : x[a + K / 2];
+    x[a] = keep + dpp_f<CTRL>(send);
+  }
+}
+
+// Sums of M values over the 16 lanes of each row, lane n of a row ending
+// with the sum for value c = n / (16 / M).  Partners, in order: n ^ 8
+// (row_ror:8), 7 - n within each half-row (row_half_mirror), n ^ 2 and
+// n ^ 1 (quad permutations); each pairs lanes whose partial sums cover
+// disjoint lane sets.  The levels that halve use the lane bits that make up
+// c; once one value is left the remaining partners add whole values.  About
+// 3 M / 2 instructions instead of the 4 M of a row all-reduce per value.
+template <int M>
+__device__ __forceinline__ float reduce_rows16(float (&x)[M], int n) {
+  constexpr int kRor8 = 0x128, kHalfMirror = 0x141, kXor2 = 0x4E, kXor1 = 0xB1;
+  if constexpr (M >= 2) halve_rows16<M, kRor8>(x, (n & 8) != 0);
+  if constexpr (M >= 4) halve_rows16<M / 2, kHalfMirror>(x, (n & 4) != 0);
+  if constexpr (M >= 8) halve_rows16<M / 4, kXor2>(x, (n & 2) != 0);
+  if constexpr (M >= 16) halve_rows16<M / 8, kXor1>(x, (n & 1) != 0);
+  float s = x[0];
+  if constexpr (M < 16) s += dpp_f<kXor1>(s);
+  if constexpr (M < 8) s += dpp_f<kXor2>(s);
+  if constexpr (M < 4) s += dpp_f<kHalfMirror>(s);
+  if constexpr (M < 2) s += dpp_f<kRor8>(s);
+  return s;
+}
+
+// Lane LANE's value broadcast to every lane of its 16-lane row
+// (row_newbcast).
+template <int LANE>
+__device__ __forceinline__ float row_bcast(float x) {
+  return dpp_f<0x150 + LANE>(x);
 }
 
 __device__ __forceinline__ int or_all(int x) {
@@ -467,6 +532,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 
   // ---------------- Algorithm 1 ----------------
   constexpr bool k16 = P != TASER_PREC_F32;
+  constexpr int M = 4 * NT;                    // column registers per lane
   u2 Ah[NT][NT];
   if constexpr (k16) {
     sfor<0, NT>([&](auto jc) {
@@ -477,13 +543,19 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       });
     });
   }
-  // Lt[it][jt][r]: row 16 it + n, column 16 jt + 4 r + g (jt <= it)
-  float Lt[NT][NT][4];
+  // Lt[it][jt][r]: row 16 it + n, column 16 jt + 4 r + g (jt <= it).  With
+  // 16-bit products the last row of L~ is row tile NT (held by the lanes
+  // n = 0; the other lanes of that tile stay zero), and its product runs on
+  // the matrix cores with the other tiles.  With float32 products it is l21
+  // (the same in every lane n), multiplied on the vector ALUs: there the
+  // extra 16x16x4 products would cost more matrix time than they save.
+  constexpr int RT = k16 ? NT + 1 : NT;
+  float Lt[RT][NT][4];
   float l21[NT][4];
   float l22 = DN;
-  sfor<0, NT>([&](auto ic) {
+  sfor<0, RT>([&](auto ic) {
     constexpr int IT = decltype(ic)::value;
-    sfor<0, IT + 1>([&](auto jc) {
+    sfor<0, (IT < NT ? IT + 1 : NT)>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -495,44 +567,82 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) l21[JT][r] = 0.f;
   });
+  // Step factor -2 tau, and on the diagonal tiles 0 for the lanes above the
+  // diagonal (L~ is zero there, so V stays zero without a select).
+  float mdg[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) mdg[r] = (4 * r + g > n) ? 0.f : m2tau;
+  // c~ where the last row lives (16-bit path: lanes n = 0 only)
+  float ce[NT][4];
+  sfor<0, NT>([&](auto jc) {
+    constexpr int JT = decltype(jc)::value;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ce[JT][r] = (k16 && n != 0) ? 0.f : ct[JT][r];
+  });
+  // After the column-norm reduction lane n holds column c = n / (16 / M) of
+  // its 16-lane row: register (c / 4, c % 4), i.e. column 16 (c / 4) +
+  // 4 (c % 4) + g.
+  const int cown = n / (16 / M);
+  const int jown = 16 * (cown / 4) + 4 * (cown % 4) + g;
+  const float Down = Dl[jown];
+  const bool aown = jown < Nm1;
+  const float f0 = n == 0 ? 1.f : 0.f;         // float32 path: the replicated last row counts once
   const bool pin = !(a.flags & TASER_FLAG_LITERAL_LAST);
   int st_bits = 0;
   const int iters = skip ? 0 : a.t_max;
   for (int t = 0; t < iters; ++t) {
-    // last row first (its product reads the old l21)
-    float lw[NT][4];
-    gemv(l21, lw);
-    const float cl = dot(l21, ct);
     float nsq[NT][4];
     sfor<0, NT>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
 #pragma unroll
       for (int r = 0; r < 4; ++r) nsq[JT][r] = 0.f;
     });
-    // L11 tiles: V = L~ - 2 tau tril(L~ T~)
-    sfor<0, NT>([&](auto ic) {
+    // last row's product (float32 path) and c~ . l21 (for V_NN), both from
+    // the old last row
+    float lw[NT][4];
+    float cl;
+    if constexpr (k16) {
+      float part = 0.f;
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part = fmaf(Lt[NT][JT][r], ce[JT][r], part);
+      });
+      // lanes n = 0 hold the last row; lane 0 has the sum over its four
+      cl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sum_quads(part))));
+    } else {
+      gemv(l21, lw);
+      cl = dot(l21, ct);
+    }
+    // V = L~ - 2 tau tril(L~ T~), row tile by row tile
+    sfor<0, RT>([&](auto ic) {
       constexpr int IT = decltype(ic)::value;
-      f4 acc[IT + 1];
+      constexpr int TM = IT < NT ? IT : NT - 1;      // last column / K tile with nonzero entries
+      f4 acc[TM + 1];
       if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
       if constexpr (k16) {
-        u2 bk[IT + 1];
-        sfor<0, IT + 1>([&](auto kc) {
+        u2 bk[TM + 1];
+        sfor<0, TM + 1>([&](auto kc) {
           constexpr int KT = decltype(kc)::value;
           bk[KT] = pack4<P>(Lt[IT][KT][0], Lt[IT][KT][1], Lt[IT][KT][2], Lt[IT][KT][3]);
         });
-        sfor<0, IT + 1>([&](auto jc) {
+        // K tiles in pairs on 16x16x32 products (the cycles of one 16x16x16)
+        sfor<0, TM + 1>([&](auto jc) {
           constexpr int JT = decltype(jc)::value;
           acc[JT] = f4{0.f, 0.f, 0.f, 0.f};
-          sfor<0, IT + 1>([&](auto kc) {
-            constexpr int KT = decltype(kc)::value;
-            acc[JT] = mfma16<P>(Ah[JT][KT], bk[KT], acc[JT]);
+          sfor<0, (TM + 2) / 2>([&](auto pc) {
+            constexpr int K0 = 2 * decltype(pc)::value;
+            if constexpr (K0 + 1 <= TM)
+              acc[JT] = mfma32<P>(Ah[JT][K0], Ah[JT][K0 + 1], bk[K0], bk[K0 + 1], acc[JT]);
+            else
+              acc[JT] = mfma16<P>(Ah[JT][K0], bk[K0], acc[JT]);
           });
         });
       } else {
-        sfor<0, IT + 1>([&](auto jc) {
+        sfor<0, TM + 1>([&](auto jc) {
           constexpr int JT = decltype(jc)::value;
           acc[JT] = f4{0.f, 0.f, 0.f, 0.f};
-          sfor<0, IT + 1>([&](auto kc) {
+          sfor<0, TM + 1>([&](auto kc) {
             constexpr int KT = decltype(kc)::value;
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc[JT] = mfma(A[JT][KT][s], Lt[IT][KT][s], acc[JT]);
@@ -540,55 +650,73 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
         });
       }
       if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(0);
-      sfor<0, IT + 1>([&](auto jc) {
+      sfor<0, TM + 1>([&](auto jc) {
         constexpr int JT = decltype(jc)::value;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          float x = fmaf(m2tau, acc[JT][r], Lt[IT][JT][r]);
-          if (IT == JT && 4 * r + g > n) x = 0.f;   // strictly upper part
+          float x;
+          if constexpr (IT == NT)         // last row: V = l21 - 2 tau (l21^T G~ + l22 c~^T)
+            x = fmaf(m2tau, fmaf(l22, ce[JT][r], acc[JT][r]), Lt[IT][JT][r]);
+          else if constexpr (IT == JT)
+            x = fmaf(mdg[r], acc[JT][r], Lt[IT][JT][r]);
+          else
+            x = fmaf(m2tau, acc[JT][r], Lt[IT][JT][r]);
           Lt[IT][JT][r] = x;
           nsq[JT][r] = fmaf(x, x, nsq[JT][r]);
         }
       });
     });
-    sfor<0, NT>([&](auto jc) {
-      constexpr int JT = decltype(jc)::value;
+    if constexpr (!k16) {
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float x = fmaf(m2tau, fmaf(l22, ct[JT][r], lw[JT][r]), l21[JT][r]);
-        l21[JT][r] = x;
-        nsq[JT][r] = sum_rows16(nsq[JT][r]) + x * x;
-      }
-    });
+        for (int r = 0; r < 4; ++r) {
+          const float x = fmaf(m2tau, fmaf(l22, ct[JT][r], lw[JT][r]), l21[JT][r]);
+          l21[JT][r] = x;
+          nsq[JT][r] = fmaf(x * f0, x, nsq[JT][r]);
+        }
+      });
+    }
     const float vnn = fmaf(m2tau, fmaf(l22, tNN, cl), l22);
     if (!(vnn > 0.f)) st_bits |= TASER_VEC_VNN_NONPOS;
-    // prox: column j <- D_j V_:,j / ||V_:,j||
-    float sc[NT][4];
-    int any_bad = 0;
+    // prox: column j <- D_j V_:,j / ||V_:,j||.  The squared norms are summed
+    // over the 16 lanes of each row by a transpose-reduction (each level
+    // halves the values a lane keeps), so that every lane ends with the norm
+    // of one column; the scale factors go back by row broadcasts.
+    float flat[M];
     sfor<0, NT>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float q = nsq[JT][r];
-        const bool ok = q > 0.f && q < 3.4e38f;
-        sc[JT][r] = (ok && act[JT][r]) ? Dc[JT][r] * __builtin_amdgcn_rsqf(q) : 0.f;
-        any_bad |= (!ok && act[JT][r]);
-      }
+      for (int r = 0; r < 4; ++r) flat[4 * JT + r] = nsq[JT][r];
     });
-    sfor<0, NT>([&](auto ic) {
+    const float q = reduce_rows16<M>(flat, n);
+    const bool ok = __builtin_amdgcn_classf(q, 0x180);   // positive normal or subnormal
+    const float sown = ok ? Down * __builtin_amdgcn_rsqf(q) : 0.f;
+    const bool any_bad = __ballot(aown && !ok) != 0ull;
+    float sc[NT][4];
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+      sfor<0, 4>([&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        sc[JT][R] = row_bcast<(4 * JT + R) * (16 / M)>(sown);
+      });
+    });
+    sfor<0, RT>([&](auto ic) {
       constexpr int IT = decltype(ic)::value;
-      sfor<0, IT + 1>([&](auto jc) {
+      sfor<0, (IT < NT ? IT + 1 : NT)>([&](auto jc) {
         constexpr int JT = decltype(jc)::value;
 #pragma unroll
         for (int r = 0; r < 4; ++r) Lt[IT][JT][r] *= sc[JT][r];
       });
     });
-    sfor<0, NT>([&](auto jc) {
-      constexpr int JT = decltype(jc)::value;
+    if constexpr (!k16) {
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) l21[JT][r] *= sc[JT][r];
-    });
-    if (__builtin_expect(__ballot(any_bad) != 0ull, 0)) {
+        for (int r = 0; r < 4; ++r) l21[JT][r] *= sc[JT][r];
+      });
+    }
+    if (__builtin_expect(any_bad, 0)) {
       // columns with zero / non-finite norm restart from D_jj e_j
       st_bits |= TASER_VEC_ZERO_NORM;
       sfor<0, NT>([&](auto jc) {
@@ -606,6 +734,14 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       l22 = DN;
       st_bits |= TASER_VEC_ZERO_NORM;
     }
+  }
+  // the last row, in the layout of the float32 path's l21 (lanes n = 0)
+  if constexpr (k16) {
+    sfor<0, NT>([&](auto jc) {
+      constexpr int JT = decltype(jc)::value;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) l21[JT][r] = Lt[NT][JT][r];
+    });
   }
 
   // ---------------- slicing and outputs ----------------
