@@ -17,7 +17,10 @@ iteration targets sigma mu (mu = <X, Z>/N) on the central path:
     (X o Z^-1) dy = 1 - sigma mu diag(Z^-1)          (o: elementwise product)
     dZ = -Diag(dy),   dX = sigma mu Z^-1 - X + X Diag(dy) Z^-1 (symmetrised)
 with step lengths 0.95 of the largest keeping X and Z positive definite
-(from the eigenvalues of L^-1 dX L^-T).  Readings where the paper is
+(from the eigenvalues of L^-1 dX L^-T).  The iteration ends at a relative
+gap of ``tol``, or earlier when X or Z no longer admits a Cholesky
+factorisation in float64 (a degenerate problem whose gap has reached the
+rounding floor; ``gap`` reports where it stopped).  Readings where the paper is
 silent: T is scaled by 1 / max|T_ij| for the solve (the argmin does not
 change); the eigenvector is oriented so that its last entry, the
 coordinate of the fixed 1 in s~, is non-negative; sign(0) = +1.
@@ -54,8 +57,11 @@ def solve_sdr(T, tol=1e-10, sigma=0.2, max_iter=200):
         dX = sigma * mu * Zi - X + X @ np.diag(dy) @ Zi
         dX = 0.5 * (dX + dX.T)
         dZ = -np.diag(dy)
-        ap = _max_step(X, dX)
-        ad = _max_step(Z, dZ)
+        try:
+            ap = _max_step(X, dX)
+            ad = _max_step(Z, dZ)
+        except np.linalg.LinAlgError:
+            break                                     # X or Z no longer factors: rounding floor reached
         X = X + min(1.0, 0.95 * ap) * dX
         y = y + min(1.0, 0.95 * ad) * dy
         Z = C - np.diag(y)
