@@ -152,6 +152,64 @@ taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void
 taser_status_t taser_solve(const taser_desc_t* desc, const float* Tt, const float* D,
                            const float* tau, float* L, int32_t* status, void* stream);
 
+/* ---- Reference detectors (Section V-A) ----------------------------------
+
+   The detectors the paper compares TASER with, on the real-valued model of
+   Section II-A (ybar = Hbar sbar + nbar, sbar in {-1,+1}^M, M = N - 1),
+   coherent requests only (desc->mode = TASER_COHERENT; B, U, mod, y_per_H,
+   num_vectors as for taser_run; t_max, prec, tau_mode and alpha unused):
+     TASER_REF_MF     the matched filter: sign(Hbar^T ybar) (Algorithm 1
+                      after one iteration has the same signs);
+     TASER_REF_MMSE   linear MMSE with unit symbol energy per real dimension:
+                      sign((Hbar^T Hbar + (n0/2) I)^-1 Hbar^T ybar), n0 >= 0
+                      the complex noise variance N0 of y = Hs + n;
+     TASER_REF_ML     exhaustive ML of eq. (1), argmin ||ybar - Hbar s||^2
+                      over all 2^M candidates, M <= 20 (ties: the candidate
+                      with the smaller bit pattern, bit j set for s_j = -1);
+     TASER_REF_KBEST  K-best breadth-first search (1 <= K <= 16) after
+                      Hbar^T Hbar = R^T R: from the last real dimension to
+                      the first each surviving path is extended by +1 and -1
+                      and the K of smallest partial distance survive (ties:
+                      the earlier candidate, path rank first, +1 first).
+   Float32 arithmetic.  Out: sbar int8 [V][M] in s~ order (sign(0) = +1);
+   soft (or NULL): MF / MMSE the estimates [V][M] before slicing, ML /
+   K-best the residual ||ybar - Hbar shat||^2 [V].  A singular Hbar^T Hbar
+   (K-best with M > 2B, or a zero channel column) does not fault: pivots
+   are clamped to the smallest normal float.  Errors: those of
+   taser_check_desc, TASER_ERR_ARG (kind, K, n0 < 0 or non-finite, NULL
+   pointers), TASER_ERR_UNSUPPORTED (JED, M > 64, ML with M > 20). */
+enum { TASER_REF_MF = 0, TASER_REF_MMSE = 1, TASER_REF_ML = 2, TASER_REF_KBEST = 3 };
+taser_status_t taser_reference_detect(const taser_desc_t* desc, int32_t kind, int32_t K, float n0,
+                                      const void* H, const void* y, int8_t* sbar, float* soft,
+                                      void* stream);
+
+/* ---- Exact semidefinite relaxation (eq. (7)) -----------------------------
+
+   The detector TASER approximates: S^ = argmin Tr(T S) subject to
+   diag(S) = 1 and S positive semidefinite, then (Section II-C) the signs
+   of the leading eigenvector of S^, oriented so that its last entry (the
+   fixed entry of s~) is non-negative; sign(0) = +1.  Both modes, 2 <= N <=
+   64 (desc: mode, B, U, mod, num_vectors as for taser_build_T; t_max,
+   prec, tau_mode, alpha unused).  Solved per vector in float64 by a
+   primal-dual interior-point method (HKM direction, adaptive centring,
+   backtracked steps at 0.95 of the boundary) until the duality gap is
+   below 1e-9 max(1, |Tr(C X)|) in the scaled units C = T / max|T_ij|, a
+   factorisation fails, the gap stalls below 1e-6 max(1, |Tr(C X)|), or
+   100 iterations.
+   In: Tt [V][N][N] and D [V][N] (float32) as taser_build_T writes them
+       (T = D T~ D), or D = NULL and Tt holding T itself; status [V] or
+       NULL (vectors with a nonzero entry are skipped: sbar = +1, X = I,
+       zeros).
+   Out: sbar int8 [V][N-1]; each of the rest may be NULL: objective [V] =
+       Tr(T X), gap [V] = Tr(T X) - sum(y) >= 0 (the duality gap, units of
+       T), X [V][N][N] (the final primal iterate), all float64;
+       iterations [V].
+   Errors: those of taser_check_desc, TASER_ERR_ARG (NULL Tt or sbar with
+   V > 0), TASER_ERR_UNSUPPORTED (N > 64). */
+taser_status_t taser_sdr_detect(const taser_desc_t* desc, const float* Tt, const float* D,
+                                const int32_t* status, int8_t* sbar, double* objective, double* gap,
+                                double* X, int32_t* iterations, void* stream);
+
 /* ---- Fixed-point mode (Section IV-C) ----------------------------------
 
    Algorithm 1 in the 14-bit fixed-point arithmetic of the paper's systolic

@@ -16,6 +16,7 @@ import os
 
 __all__ = ["TaserError", "load", "problem_size", "build_T", "solve", "detect", "run",
            "BPSK", "QPSK", "COHERENT", "JED", "PREC_F32", "PREC_BF16", "PREC_F16", "PREC_FIXED14",
+           "REF_MF", "REF_MMSE", "REF_ML", "REF_KBEST", "reference_detect", "sdr_detect",
            "TAU_SPECTRAL", "TAU_GIVEN", "workspace_size", "run_prep", "run_solve", "run_tau", "calibrate", "jed_channel", "run_mixed", "FLAG_LITERAL_LAST", "VEC_DEGENERATE",
            "VEC_NONFINITE", "VEC_ZERO_NORM", "VEC_VNN_NONPOS", "LIB_PATH", "UnfoldedDesc",
            "unfolded_sizes", "unfolded_forward", "unfolded_backward"]
@@ -109,6 +110,10 @@ def load():
     lib.taser_fixed_quantize.argtypes = [D, _P, _P, _P, _P, _P, _P]
     lib.taser_fixed_solve.restype = ctypes.c_int
     lib.taser_fixed_solve.argtypes = [D, _P, _P, _P, _P, _P, _P]
+    lib.taser_reference_detect.restype = ctypes.c_int
+    lib.taser_reference_detect.argtypes = [D, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _P, _P, _P, _P, _P]
+    lib.taser_sdr_detect.restype = ctypes.c_int
+    lib.taser_sdr_detect.argtypes = [D, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     lib.taser_jed_channel.restype = ctypes.c_int
     lib.taser_jed_channel.argtypes = [D, _P, _P, _P, _P, _P]
     lib.taser_calibrate.restype = ctypes.c_int
@@ -278,6 +283,52 @@ def fixed_solve(desc: Desc, That, Dq, status):
                                  _need(out["L"], torch.int16, V * N * (N + 1) // 2, "L"),
                                  _need(out["sbar"], torch.int8, V * (N - 1), "sbar"),
                                  _need(status, torch.int32, V, "status"), _stream(That.device)))
+    return out
+
+
+REF_MF, REF_MMSE, REF_ML, REF_KBEST = 0, 1, 2, 3
+
+
+def reference_detect(desc: Desc, kind: int, H, y, K: int = 5, n0: float = 0.0, want_soft=False):
+    """Reference detectors (``taser_reference_detect``): returns (sbar int8
+    [V, N-1], soft or None); soft is the estimate [V, N-1] (MF, MMSE) or the
+    residual [V] (ML, K-best)."""
+    torch = _torch()
+    lib = load()
+    V, M = desc.num_vectors, problem_size(desc.U, desc.mod) - 1
+    dev = y.device
+    ph, py, _ = _inputs(desc, H, y, None)
+    sbar = torch.empty((V, M), dtype=torch.int8, device=dev)
+    soft = None
+    if want_soft:
+        soft = torch.empty((V, M) if kind in (REF_MF, REF_MMSE) else (V,), dtype=torch.float32, device=dev)
+    _raise(lib.taser_reference_detect(ctypes.byref(desc), int(kind), int(K), float(n0), ph, py,
+                                      _need(sbar, torch.int8, V * M, "sbar"),
+                                      None if soft is None else ctypes.c_void_p(soft.data_ptr()), _stream(dev)))
+    return sbar, soft
+
+
+def sdr_detect(desc: Desc, Tt, D=None, status=None, want_X=False):
+    """Exact SDR detector of eq. (7) (``taser_sdr_detect``) on T = D T~ D
+    (``Tt``, ``D`` as ``build_T`` returns them) or, with ``D=None``, on
+    ``Tt`` = T itself (float32).  Returns dict sbar [V, N-1], objective [V],
+    gap [V], iterations [V] and, with ``want_X``, X [V, N, N] (float64)."""
+    torch = _torch()
+    lib = load()
+    V, N = desc.num_vectors, problem_size(desc.U, desc.mod)
+    dev = Tt.device
+    out = {"sbar": torch.empty((V, N - 1), dtype=torch.int8, device=dev),
+           "objective": torch.empty((V,), dtype=torch.float64, device=dev),
+           "gap": torch.empty((V,), dtype=torch.float64, device=dev),
+           "iterations": torch.empty((V,), dtype=torch.int32, device=dev)}
+    if want_X:
+        out["X"] = torch.empty((V, N, N), dtype=torch.float64, device=dev)
+    _raise(lib.taser_sdr_detect(ctypes.byref(desc), _need(Tt, torch.float32, V * N * N, "Tt"),
+                                _opt(D, torch.float32, V * N, "D"), _opt(status, torch.int32, V, "status"),
+                                ctypes.c_void_p(out["sbar"].data_ptr()), ctypes.c_void_p(out["objective"].data_ptr()),
+                                ctypes.c_void_p(out["gap"].data_ptr()),
+                                ctypes.c_void_p(out["X"].data_ptr()) if want_X else None,
+                                ctypes.c_void_p(out["iterations"].data_ptr()), _stream(dev)))
     return out
 
 

@@ -180,6 +180,43 @@ taser_status_t taser_fixed_solve(const taser_desc_t* desc, const int16_t* That, 
   return launch_status([&] { return launch_fixed_solve(f, static_cast<hipStream_t>(stream)); });
 }
 
+taser_status_t taser_reference_detect(const taser_desc_t* desc, int32_t kind, int32_t K, float n0,
+                                      const void* H, const void* y, int8_t* sbar, float* soft,
+                                      void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  if (kind < TASER_REF_MF || kind > TASER_REF_KBEST) return TASER_ERR_ARG;
+  if (kind == TASER_REF_KBEST && (K < 1 || K > 16)) return TASER_ERR_ARG;
+  if (kind == TASER_REF_MMSE && !(n0 >= 0.f && isfinite(n0))) return TASER_ERR_ARG;
+  if (desc->mode != TASER_COHERENT) return TASER_ERR_UNSUPPORTED;
+  const int M = taser_problem_size(desc->U, desc->mod) - 1;
+  if (M > 64 || (kind == TASER_REF_ML && M > 20)) return TASER_ERR_UNSUPPORTED;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!H || !y || !sbar) return TASER_ERR_ARG;
+  RefArgs r{};
+  r.V = desc->num_vectors; r.B = desc->B; r.U = desc->U; r.M = M; r.mod = desc->mod;
+  r.y_per_H = desc->y_per_H; r.kind = kind; r.K = K; r.n0 = n0;
+  r.H = static_cast<const float2*>(H);
+  r.y = static_cast<const float2*>(y);
+  r.sbar = sbar; r.soft = soft;
+  return launch_status([&] { return launch_reference(r, static_cast<hipStream_t>(stream)); });
+}
+
+taser_status_t taser_sdr_detect(const taser_desc_t* desc, const float* Tt, const float* D,
+                                const int32_t* status, int8_t* sbar, double* objective, double* gap,
+                                double* X, int32_t* iterations, void* stream) {
+  taser_status_t st = check(desc);
+  if (st != TASER_OK) return st;
+  const int N = taser_problem_size(desc->U, desc->mod);
+  if (N > 64) return TASER_ERR_UNSUPPORTED;
+  if (desc->num_vectors == 0) return TASER_OK;
+  if (!Tt || !sbar) return TASER_ERR_ARG;
+  SdrArgs r{};
+  r.V = desc->num_vectors; r.N = N; r.Tt = Tt; r.D = D; r.status = status; r.sbar = sbar;
+  r.objective = objective; r.gap = gap; r.X = X; r.iterations = iterations;
+  return launch_status([&] { return launch_sdr(r, static_cast<hipStream_t>(stream)); });
+}
+
 taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const void* s0,
                                  const int8_t* sbar, void* h, void* stream) {
   taser_status_t st = check(desc);

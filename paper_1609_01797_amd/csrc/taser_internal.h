@@ -83,6 +83,32 @@ hipError_t launch_fixed_quantize(const FixedArgs& a, const float* Tt, const floa
                                  const float* tau, int16_t* That, int16_t* Dq, hipStream_t s);
 hipError_t launch_fixed_solve(const FixedArgs& a, hipStream_t s);
 
+// Reference detectors of the comparison (Section V-A): matched filter, MMSE,
+// exhaustive ML, K-best.  M = N - 1 real dimensions.
+struct RefArgs {
+  int32_t V, B, U, M, mod, y_per_H, kind, K;
+  float n0;
+  const float2* H;
+  const float2* y;
+  int8_t* sbar;        // [V][M]
+  float* soft;         // MF / MMSE: [V][M] estimates; ML / K-best: [V] residual; or NULL
+};
+hipError_t launch_reference(const RefArgs& a, hipStream_t s);
+
+// Exact SDR of eq. (7) in float64, one wave per vector, 2 <= N <= 64.
+struct SdrArgs {
+  int32_t V, N;
+  const float* Tt;          // [V][N][N]
+  const float* D;           // [V][N], or NULL when Tt holds T itself
+  const int32_t* status;    // [V] or NULL: nonzero entries are skipped
+  int8_t* sbar;             // [V][N-1]
+  double* objective;        // [V] or NULL
+  double* gap;              // [V] or NULL
+  double* X;                // [V][N][N] or NULL
+  int32_t* iterations;      // [V] or NULL
+};
+hipError_t launch_sdr(const SdrArgs& a, hipStream_t s);
+
 // Mixed-size batches: per-vector sizes and offsets, and the bucket lists in
 // the workspace (count[kMixedBuckets] then kMixedBuckets lists of V indices).
 constexpr int kMixedBuckets = 3;

@@ -322,3 +322,43 @@ def test_fixed_point_entry_points_reject_before_any_launch():
     empty = taser.make_desc(0, 32, 8, taser.QPSK, t_max=10)
     assert lib.taser_fixed_quantize(ctypes.byref(empty), z, z, z, z, z, z) == taser.OK
     assert lib.taser_fixed_solve(ctypes.byref(empty), z, z, z, z, z, z) == taser.OK
+
+
+def test_reference_detect_rejects_before_any_launch():
+    lib = taser.load()
+    z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)
+    d = taser.make_desc(8, 16, 8, taser.QPSK)
+    call = lambda desc, kind, K=5, n0=0.0, sb=one: lib.taser_reference_detect(  # noqa: E731
+        ctypes.byref(desc), kind, K, n0, one, one, sb, None, z)
+    assert call(d, 7) == taser.ERR_ARG
+    assert call(d, taser.REF_KBEST, K=0) == taser.ERR_ARG
+    assert call(d, taser.REF_KBEST, K=17) == taser.ERR_ARG
+    assert call(d, taser.REF_MMSE, n0=-1.0) == taser.ERR_ARG
+    assert call(d, taser.REF_MMSE, n0=float("inf")) == taser.ERR_ARG
+    assert call(d, taser.REF_MF, sb=z) == taser.ERR_ARG
+    assert call(taser.make_desc(8, 16, 8, taser.QPSK, mode=taser.JED), taser.REF_MF) == taser.ERR_UNSUPPORTED
+    assert call(taser.make_desc(8, 16, 33, taser.QPSK), taser.REF_MF) == taser.ERR_UNSUPPORTED   # M = 66
+    assert call(taser.make_desc(8, 16, 11, taser.QPSK), taser.REF_ML) == taser.ERR_UNSUPPORTED   # M = 22
+    taser.inject_device_error(1)
+    try:
+        assert call(d, taser.REF_KBEST) == taser.ERR_DEVICE
+    finally:
+        taser.inject_device_error(0)
+
+
+def test_sdr_detect_rejects_before_any_launch():
+    lib = taser.load()
+    z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)
+    call = lambda desc, Tt=one, sb=one: lib.taser_sdr_detect(  # noqa: E731
+        ctypes.byref(desc), Tt, None, None, sb, None, None, None, None, z)
+    assert call(taser.make_desc(4, 64, 32, taser.QPSK)) == taser.ERR_UNSUPPORTED   # N = 65
+    assert call(taser.make_desc(4, 64, 64, taser.BPSK)) == taser.ERR_UNSUPPORTED   # N = 65
+    assert call(taser.make_desc(0, 16, 8, taser.QPSK), Tt=z, sb=z) == taser.OK
+    assert call(taser.make_desc(2, 16, 8, taser.QPSK), Tt=z) == taser.ERR_ARG
+    assert call(taser.make_desc(2, 16, 8, taser.QPSK), sb=z) == taser.ERR_ARG
+    assert call(taser.make_desc(2, 16, 0, taser.QPSK)) == taser.ERR_SHAPE           # check_desc
+    taser.inject_device_error(1)
+    try:
+        assert call(taser.make_desc(2, 16, 8, taser.QPSK)) == taser.ERR_DEVICE
+    finally:
+        taser.inject_device_error(0)
