@@ -127,8 +127,12 @@ def run_mixed_workload(args):
         desc = taser.make_desc(V, 1, 1, 2, prec=prec, t_max=t_max, alpha=alpha)
         ws = torch.empty(1 << 24, dtype=torch.uint8, device=dev)
         out = {}
-        call = lambda blocks=None: taser.run_mixed(desc, *ins, blocks=blocks, out=out, ws=ws)  # noqa: E731
+        def call(cfg=None):
+            cfg = cfg or autotune.DEFAULT
+            return taser.run_mixed(desc, *ins, blocks=cfg["blocks"], waves=cfg["waves"],
+                                   single=bool(cfg["single"]), out=out, ws=ws)
         ms_default = _time(lambda: call(None), args.steps, args.warmup, stream)
+        ms_single = _time(lambda: call(dict(autotune.DEFAULT, single=1)), args.steps, args.warmup, stream)
         best, tune_report, trace = autotune.tune_mixed(desc, ins, reps=3)
         ms_tuned = _time(lambda: call(best), args.steps, args.warmup, stream)
         # graph replay of the tuned call
@@ -144,8 +148,8 @@ def run_mixed_workload(args):
         for c, (idx, rsb) in samp.items():
             fl += int(np.count_nonzero(sb[idx, :rsb.shape[1]] != rsb))
         flips[name] = fl
-        paths[name] = {"ms_default": ms_default, "ms_tuned": ms_tuned, "ms_graph": ms_graph,
-                       "tuned_blocks": best, "autotune": tune_report,
+        paths[name] = {"ms_default": ms_default, "ms_single_launch": ms_single, "ms_tuned": ms_tuned,
+                       "ms_graph": ms_graph, "tuned": best, "autotune": tune_report,
                        "vectors_per_s": V / (min(ms_tuned, ms_graph) * 1e-3),
                        "ber": err / int(mask.sum())}
     # algorithmic flops per vector, averaged over the batch

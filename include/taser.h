@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TASER_ABI_VERSION 1
+#define TASER_ABI_VERSION 2
 #define TASER_MAX_N 129          /* largest problem size N the library accepts */
 #define TASER_MAX_VECTORS (1 << 30) /* largest num_vectors any entry point accepts
                                        (kernel indices stay within 32 bits) */
@@ -361,11 +361,21 @@ int32_t taser_calibrate_elements(void);
    [V][stride] (or NULL): the first N_v - 1 entries of row v are the
    decisions / margins, the rest of the row is 0; status [V].  Vectors with U_v > 32 or N_v - 1 > 64 get status
    TASER_VEC_UNSUPPORTED.  All per-vector arrays are device arrays. */
-/* Grid per size bucket: 0 (the default) launches one workgroup per vector of
-   the batch, those past the bucket's count exit at once; n > 0 launches a
-   persistent grid of n workgroups that walk the bucket's list.  NULL = all 0. */
+/* Launch choices (NULL = all 0, the defaults), results do not depend on them:
+     blocks[b]  grid of size bucket b: 0 launches one workgroup per vector of
+                the batch, those past the bucket's count exit at once; n > 0
+                (at most 2^20) a persistent grid of n workgroups that walk
+                the bucket's list;
+     waves[b]   register budget of bucket b's one-workgroup-per-vector
+                kernel: 0 the default build, 1 the alternative (8 waves per
+                SIMD for N-1 <= 16, 4 for <= 32, 3 for <= 64);
+     single_launch  1: every bucket in one launch over one work queue (the
+                bucket lists, largest problems first), with the registers of
+                the largest size; blocks and waves are then ignored. */
 typedef struct {
   int32_t blocks[3];
+  int32_t waves[3];
+  int32_t single_launch;
 } taser_mixed_launch_t;
 
 taser_status_t taser_mixed_workspace_size(const taser_desc_t* desc, size_t* bytes);

@@ -1,14 +1,18 @@
 """Launch-configuration autotuner for the mixed-size batch path.
 
-The tunable knob is the grid of each size bucket (N-1 <= 16, <= 32, <= 64):
-0 = one one-wave workgroup per vector of the batch (the library default),
-n > 0 = a persistent grid of n workgroups walking the bucket's vector list.
-The persistent kernel saves workgroup launches but carries its loop's state
-in registers; which wins depends on the bucket and the batch.
-``tune_mixed`` times candidate grids on the device for one bucket at
-a time (coordinate descent, the other buckets at their current best), keeps
-the fastest, and caches the result in a JSON file keyed by GPU architecture,
-bucket, precision and t_max.  Timing uses HIP events on the launch stream.
+The choices, per size bucket (N-1 <= 16, <= 32, <= 64), are the grid
+(0 = one one-wave workgroup per vector of the batch, the library default;
+n > 0 = a persistent grid of n workgroups walking the bucket's vector list)
+and the register budget of the one-workgroup-per-vector kernel (0 = the
+default build, 1 = the alternative: more waves per SIMD for one and four
+column tiles, fewer for two); and, for the whole batch, a single launch of
+one kernel over one work queue with the registers of the largest size.
+``tune_mixed`` searches them on the device by coordinate descent (one
+choice at a time, the others at their current best, short timings), then
+times the proposal and the default interleaved and adopts the proposal only
+if its median beats the default's p10.  The result is cached in a JSON file
+keyed by GPU architecture, precision, t_max and batch-size class.  Timing
+uses HIP events on the launch stream.
 """
 from __future__ import annotations
 
@@ -28,12 +32,12 @@ def _arch():
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
-def cache_key(bucket, prec, t_max, num_vectors):
-    """Key of a tuned grid: architecture, bucket, precision, t_max and the
-    batch size class (log2 of the vector count: the best persistent grid
-    depends on how many vectors each bucket holds)."""
+def cache_key(prec, t_max, num_vectors):
+    """Key of a tuned configuration: architecture, precision, t_max and the
+    batch size class (log2 of the vector count: the best grids depend on how
+    many vectors each bucket holds)."""
     size_class = max(int(num_vectors), 1).bit_length()
-    return f"{_arch()}|mixed|b{bucket}|p{prec}|t{t_max}|v2^{size_class}"
+    return f"{_arch()}|mixed|p{prec}|t{t_max}|v2^{size_class}"
 
 
 def load_cache(path=DEFAULT_CACHE):
@@ -53,11 +57,15 @@ def save_cache(cache, path=DEFAULT_CACHE):
         os.replace(tmp, path)
 
 
-def cached_blocks(prec, t_max, num_vectors, path=DEFAULT_CACHE):
-    """Tuned grid per bucket from the cache (0 = library default)."""
-    cache = load_cache(path)
-    return [int(cache.get(cache_key(b, prec, t_max, num_vectors), {}).get("blocks", 0))
-            for b in range(3)]
+DEFAULT = {"blocks": [0, 0, 0], "waves": [0, 0, 0], "single": 0}
+
+
+def cached_config(prec, t_max, num_vectors, path=DEFAULT_CACHE):
+    """Tuned launch choices from the cache (the defaults when absent)."""
+    rec = load_cache(path).get(cache_key(prec, t_max, num_vectors))
+    if not rec:
+        return dict(DEFAULT)
+    return {"blocks": list(rec["blocks"]), "waves": list(rec["waves"]), "single": int(rec["single"])}
 
 
 def _time_call(fn, reps=5):
@@ -92,49 +100,64 @@ def compare(fn_a, fn_b, rounds=15, reps=3):
     return _stats(ta), _stats(tb)
 
 
-def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sweeps=1, rounds=15):
-    """Tune the per-bucket grid of ``run_mixed(desc, *args)`` and store it.
+def _key(cfg):
+    return (tuple(cfg["blocks"]), tuple(cfg["waves"]), cfg["single"])
 
-    Coordinate descent over the buckets with short timings proposes a
-    winner (a candidate equal to the current best is not timed again).  The
-    winner and the default are then timed interleaved over ``rounds``
-    rounds; the winner is adopted only if its median beats the default's
-    p10 (faster than the default's spread), otherwise the default is kept.
-    Returns (blocks, {"default": stats, "tuned": stats, "adopted": bool,
-    "proposed": blocks}, trace)."""
+
+def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sweeps=1, rounds=15):
+    """Tune the launch choices of ``run_mixed(desc, *args)`` and store them.
+
+    Coordinate descent with short timings proposes a configuration (a choice
+    equal to the current best is not timed again); the proposal and the
+    default are then timed interleaved over ``rounds`` rounds and the
+    proposal is adopted only if its median beats the default's p10.
+    Returns (config, {"default": stats, "tuned": stats, "adopted": bool,
+    "proposed": config}, trace)."""
     import paper_1609_01797_amd as taser
     out = {}
 
-    def call(blocks):
-        return lambda: taser.run_mixed(desc, *args, blocks=blocks, out=out)
+    def call(cfg):
+        return lambda: taser.run_mixed(desc, *args, blocks=cfg["blocks"], waves=cfg["waves"],
+                                       single=bool(cfg["single"]), out=out)
 
-    best = [0, 0, 0]
+    def variant(cfg, field, b, value):
+        new = {"blocks": list(cfg["blocks"]), "waves": list(cfg["waves"]), "single": cfg["single"]}
+        if field == "single":
+            new["single"] = value
+        else:
+            new[field][b] = value
+        return new
+
+    best = dict(DEFAULT, blocks=[0, 0, 0], waves=[0, 0, 0])
     best_ms = _time_call(call(best), reps)
-    trace = [{"blocks": list(best), "ms": best_ms}]
+    seen = {_key(best): best_ms}
+    trace = [{"config": best, "ms": best_ms}]
+    choices = [("single", 0, (0, 1))]
+    for b in range(3):
+        choices += [("blocks", b, candidates), ("waves", b, (0, 1))]
     for _ in range(sweeps):
-        for b in range(3):
-            for c in candidates:
-                if c == best[b]:
+        for field, b, values in choices:
+            for value in values:
+                trial = variant(best, field, b, value)
+                if _key(trial) in seen:
                     continue
-                trial = list(best)
-                trial[b] = c
                 ms = _time_call(call(trial), reps)
-                trace.append({"blocks": trial, "ms": ms})
+                seen[_key(trial)] = ms
+                trace.append({"config": trial, "ms": ms})
                 if ms < best_ms:
                     best_ms, best = ms, trial
-    default = [0, 0, 0]
-    if best == default:
+    default = dict(DEFAULT, blocks=[0, 0, 0], waves=[0, 0, 0])
+    if _key(best) == _key(default):
         st, _ = compare(call(default), call(default), rounds=max(rounds // 3, 3), reps=reps)
         report = {"default": st, "tuned": st, "adopted": False, "proposed": default}
     else:
         st_d, st_t = compare(call(default), call(best), rounds=rounds, reps=reps)
         adopted = st_t["median_ms"] < st_d["p10_ms"]
-        report = {"default": st_d, "tuned": st_t, "adopted": adopted, "proposed": list(best)}
+        report = {"default": st_d, "tuned": st_t, "adopted": adopted, "proposed": best}
         if not adopted:
             best = default
     cache = load_cache(path)
-    for b in range(3):
-        cache[cache_key(b, desc.prec, desc.t_max, desc.num_vectors)] = {
-            "blocks": best[b], "median_ms": report["tuned" if report["adopted"] else "default"]["median_ms"]}
+    cache[cache_key(desc.prec, desc.t_max, desc.num_vectors)] = dict(
+        best, median_ms=report["tuned" if report["adopted"] else "default"]["median_ms"])
     save_cache(cache, path)
     return best, report, trace

@@ -232,20 +232,18 @@ struct VecJob {
   int pad_to;             // mixed batches: entries N-1 .. pad_to-1 of sbar/margin are set to 0
 };
 
+// T (eq. (2) coherent, eq. (5) joint detection) of one vector into LDS T
+// [(16 NT + 1)^2] in padded indexing (real index i < N - 1 -> i, N - 1 ->
+// 16 NT; the padding rows and columns are zero).  One wave; ends with a
+// barrier.
 template <int NT, int P>
-__device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, float* lds) {
+__device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* T) {
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
-  float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
-  float* Dl = lds + S::REGION;           // [N1+1]
-  float* sh = Dl + (N1 + 1);             // [N1] layout shuffle
-
   const int lane = threadIdx.x;
   const int n = lane & 15;
   const int g = lane >> 4;
-  const long long v = job.v;
-  const int B = job.B, U = job.U, Nm1 = job.N - 1;
-  const bool jed = a.mode == TASER_JED;
+  const int B = job.B, U = job.U;
   const bool qpsk = job.mod == TASER_QPSK;
   const float sg = jed ? -1.f : 1.f;
 
@@ -289,48 +287,59 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     }
   };
   const int quads = (B + 3) / 4;
-  load_batch(0, hc, yc);
-  for (int q0 = 0; q0 < quads; q0 += kQ) {
-    if (q0 + kQ < quads) load_batch(q0 + kQ, hn, yn);
+  // BPSK needs only Re G and Re b (T uses the real parts), so its row loop
+  // issues half the Gram MFMAs; the modulation is the same in every lane
+  auto rows = [&](auto qc) {
+    constexpr bool Q = decltype(qc)::value;
+    load_batch(0, hc, yc);
+    for (int q0 = 0; q0 < quads; q0 += kQ) {
+      if (q0 + kQ < quads) load_batch(q0 + kQ, hn, yn);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const float2 h0 = hc[q][0], y = yc[q];
-      // float32 products: issue priority while this wave feeds the matrix
-      // pipe (here and in the tril products below); with 16-bit products it
-      // made mixed batches slower
-      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
-      gre[0] = mfma(h0.x, h0.x, gre[0]);       // Re G = Hr^T Hr + Hi^T Hi
-      gre[0] = mfma(h0.y, h0.y, gre[0]);
-      gim[0] = mfma(h0.x, h0.y, gim[0]);       // Im G = Hr^T Hi - Hi^T Hr
-      gim[0] = mfma(h0.y, -h0.x, gim[0]);
-      if constexpr (UTM == 2) {
-        if (UT == 2) {
-          const float2 h1 = hc[q][1];
-          gre[1] = mfma(h1.x, h0.x, gre[1]);
-          gre[1] = mfma(h1.y, h0.y, gre[1]);
-          gim[1] = mfma(h1.x, h0.y, gim[1]);
-          gim[1] = mfma(h1.y, -h0.x, gim[1]);
-          gre[2] = mfma(h1.x, h1.x, gre[2]);
-          gre[2] = mfma(h1.y, h1.y, gre[2]);
-          gim[2] = mfma(h1.x, h1.y, gim[2]);
-          gim[2] = mfma(h1.y, -h1.x, gim[2]);
+      for (int q = 0; q < kQ; ++q) {
+        const float2 h0 = hc[q][0], y = yc[q];
+        // float32 products: issue priority while this wave feeds the matrix
+        // pipe (here and in the tril products below); with 16-bit products it
+        // made mixed batches slower
+        if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
+        gre[0] = mfma(h0.x, h0.x, gre[0]);       // Re G = Hr^T Hr + Hi^T Hi
+        gre[0] = mfma(h0.y, h0.y, gre[0]);
+        if constexpr (Q) {
+          gim[0] = mfma(h0.x, h0.y, gim[0]);     // Im G = Hr^T Hi - Hi^T Hr
+          gim[0] = mfma(h0.y, -h0.x, gim[0]);
         }
+        if constexpr (UTM == 2) {
+          if (UT == 2) {
+            const float2 h1 = hc[q][1];
+            gre[1] = mfma(h1.x, h0.x, gre[1]);
+            gre[1] = mfma(h1.y, h0.y, gre[1]);
+            gre[2] = mfma(h1.x, h1.x, gre[2]);
+            gre[2] = mfma(h1.y, h1.y, gre[2]);
+            if constexpr (Q) {
+              gim[1] = mfma(h1.x, h0.y, gim[1]);
+              gim[1] = mfma(h1.y, -h0.x, gim[1]);
+              gim[2] = mfma(h1.x, h1.y, gim[2]);
+              gim[2] = mfma(h1.y, -h1.x, gim[2]);
+            }
+          }
+        }
+        if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+        for (int t = 0; t < UTM; ++t) {          // conj(h) y
+          bre[t] = fmaf(hc[q][t].x, y.x, fmaf(hc[q][t].y, y.y, bre[t]));
+          if constexpr (Q) bim[t] = fmaf(hc[q][t].x, y.y, fmaf(-hc[q][t].y, y.x, bim[t]));
+        }
+        ysq = fmaf(y.x, y.x, fmaf(y.y, y.y, ysq));
       }
-      if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-      for (int t = 0; t < UTM; ++t) {          // conj(h) y
-        bre[t] = fmaf(hc[q][t].x, y.x, fmaf(hc[q][t].y, y.y, bre[t]));
-        bim[t] = fmaf(hc[q][t].x, y.y, fmaf(-hc[q][t].y, y.x, bim[t]));
+      for (int q = 0; q < kQ; ++q) {
+        yc[q] = yn[q];
+#pragma unroll
+        for (int t = 0; t < UTM; ++t) hc[q][t] = hn[q][t];
       }
-      ysq = fmaf(y.x, y.x, fmaf(y.y, y.y, ysq));
     }
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      yc[q] = yn[q];
-#pragma unroll
-      for (int t = 0; t < UTM; ++t) hc[q][t] = hn[q][t];
-    }
-  }
+  };
+  if (qpsk) rows(std::true_type{});
+  else rows(std::false_type{});
 #pragma unroll
   for (int t = 0; t < UTM; ++t) { bre[t] = sum_quads(bre[t]); bim[t] = sum_quads(bim[t]); }
   ysq = sum_quads(ysq);                        // rows 4 q + g summed over the four g lanes
@@ -373,6 +382,27 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   }
   if (lane == 0) T[N1 * LD + N1] = sg * ysq;
   __syncthreads();
+}
+
+template <int NT, int P>
+__device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, float* lds) {
+  constexpr int N1 = 16 * NT;
+  using S = VecLds<NT>;
+  float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
+  float* Dl = lds + S::REGION;           // [N1+1]
+  float* sh = Dl + (N1 + 1);             // [N1] layout shuffle
+
+  const int lane = threadIdx.x;
+  const int n = lane & 15;
+  const int g = lane >> 4;
+  const long long v = job.v;
+  const int B = job.B, U = job.U, Nm1 = job.N - 1;
+  const bool jed = a.mode == TASER_JED;
+  const bool qpsk = job.mod == TASER_QPSK;
+  const float sg = jed ? -1.f : 1.f;
+
+  vec_build_T<NT, P>(job, jed, T);
+  constexpr int LD = N1 + 1;
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
   int bad = 0, deg = 0;
@@ -802,6 +832,14 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 // dependency chain.  Six would need 80 and spill.
 template <int NT>
 constexpr int kVecWaves = NT == 2 ? 5 : 1;
+// The alternative register budgets the mixed-batch launch can select per
+// size bucket (taser_mixed_launch_t.waves): eight waves per SIMD for one
+// tile (64 VGPRs), four for two tiles (128, room for the scheduler), three
+// for four tiles (168 instead of ~200).
+template <int NT>
+constexpr int kAltWaves = NT == 1 ? 8 : (NT == 2 ? 4 : 3);
+template <int NT, int W>
+constexpr int kMixedWaves = W ? kAltWaves<NT> : kVecWaves<NT>;
 
 // One vector per block (uniform sizes).
 template <int NT, int P>
@@ -866,12 +904,8 @@ __global__ __launch_bounds__(64) void fused_vec_mixed(FusedArgs a, MixedArgs m, 
 // once.  Without the persistent loop the body keeps its registers to itself
 // (the loop made the compiler keep loop-invariant index arithmetic live
 // through every vector: 198 instead of 107 VGPRs for N-1 <= 32).
-template <int NT, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kVecWaves<NT>)))
-void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
-  __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
-  const int item = blockIdx.x;
-  if (item >= m.count[bucket]) return;
+__device__ __forceinline__ VecJob mixed_job(const FusedArgs& a, const MixedArgs& m, int bucket,
+                                            int item) {
   VecJob job;
   job.v = m.list[(long long)bucket * a.V + item];
   job.B = m.Bv[job.v]; job.U = m.Uv[job.v]; job.mod = m.modv[job.v];
@@ -883,7 +917,35 @@ void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
   job.margin = a.margin ? a.margin + job.v * (long long)m.stride : nullptr;
   job.L = nullptr;
   job.pad_to = m.stride;
-  vec_body<NT, P>(a, job, lds);
+  return job;
+}
+
+template <int NT, int P, int W>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMixedWaves<NT, W>)))
+void fused_vec_mixed_once(FusedArgs a, MixedArgs m, int bucket) {
+  __shared__ __align__(16) float lds[VecLds<NT>::FLOATS];
+  const int item = blockIdx.x;
+  if (item >= m.count[bucket]) return;
+  vec_body<NT, P>(a, mixed_job(a, m, bucket, item), lds);
+}
+
+// Every bucket in one launch: workgroup i takes entry i of one work queue,
+// the bucket lists in the order N - 1 <= 64, <= 32, <= 16 (the longest
+// problems start first and the short ones fill the tail).  The body of each
+// size is compiled into the one kernel, which therefore runs with the
+// registers and LDS of the largest.
+template <int P>
+__global__ __launch_bounds__(64) void fused_vec_mixed_all(FusedArgs a, MixedArgs m) {
+  __shared__ __align__(16) float lds[VecLds<4>::FLOATS];
+  const int c2 = m.count[2], c1 = m.count[1], c0 = m.count[0];
+  int item = blockIdx.x;
+  if (item < c2) {
+    vec_body<4, P>(a, mixed_job(a, m, 2, item), lds);
+  } else if ((item -= c2) < c1) {
+    vec_body<2, P>(a, mixed_job(a, m, 1, item), lds);
+  } else if ((item -= c1) < c0) {
+    vec_body<1, P>(a, mixed_job(a, m, 0, item), lds);
+  }
 }
 
 // Size bucket of a mixed-batch vector: 0 = N-1 <= 16, 1 = <= 32, 2 = <= 64,
@@ -938,10 +1000,23 @@ __global__ void mixed_assign(FusedArgs a, MixedArgs m) {
   }
 }
 
+template <int NT, int W>
+void launch_mixed_once(const FusedArgs& a, const MixedArgs& m, int bucket, hipStream_t s) {
+  const dim3 grid(a.V), block(64);
+  if (a.prec == TASER_PREC_BF16)
+    hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_BF16, W>), grid, block, 0, s, a, m, bucket);
+  else if (a.prec == TASER_PREC_F16)
+    hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F16, W>), grid, block, 0, s, a, m, bucket);
+  else
+    hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F32, W>), grid, block, 0, s, a, m, bucket);
+}
+
 // blocks > 0: a persistent grid of that many workgroups; 0: one workgroup
-// per entry of the batch (the default).
+// per entry of the batch (the default), compiled for the default (waves 0)
+// or the alternative (waves 1) register budget.
 template <int NT>
-bool launch_mixed_nt(const FusedArgs& a, const MixedArgs& m, int bucket, int blocks, hipStream_t s) {
+bool launch_mixed_nt(const FusedArgs& a, const MixedArgs& m, int bucket, int blocks, int waves,
+                     hipStream_t s) {
   const dim3 block(64);
   if (blocks > 0) {
     const dim3 grid(blocks);
@@ -951,14 +1026,10 @@ bool launch_mixed_nt(const FusedArgs& a, const MixedArgs& m, int bucket, int blo
       hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
     else
       hipLaunchKernelGGL((fused_vec_mixed<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+  } else if (waves) {
+    launch_mixed_once<NT, 1>(a, m, bucket, s);
   } else {
-    const dim3 grid(a.V);
-    if (a.prec == TASER_PREC_BF16)
-      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_BF16>), grid, block, 0, s, a, m, bucket);
-    else if (a.prec == TASER_PREC_F16)
-      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F16>), grid, block, 0, s, a, m, bucket);
-    else
-      hipLaunchKernelGGL((fused_vec_mixed_once<NT, TASER_PREC_F32>), grid, block, 0, s, a, m, bucket);
+    launch_mixed_once<NT, 0>(a, m, bucket, s);
   }
   return true;
 }
@@ -981,14 +1052,26 @@ size_t mixed_workspace_bytes(int V) {
   return 256 + (size_t)kMixedBuckets * (size_t)V * sizeof(int32_t);
 }
 
-hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s) {
+hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const taser_mixed_launch_t* launch,
+                        hipStream_t s) {
   hipLaunchKernelGGL(mixed_clear, dim3(1), dim3(64), 0, s, m.count);
   hipLaunchKernelGGL(mixed_assign, dim3((a.V + 255) / 256), dim3(256), 0, s, a, m);
+  if (launch && launch->single_launch) {
+    const dim3 grid(a.V), block(64);
+    if (a.prec == TASER_PREC_BF16)
+      hipLaunchKernelGGL(fused_vec_mixed_all<TASER_PREC_BF16>, grid, block, 0, s, a, m);
+    else if (a.prec == TASER_PREC_F16)
+      hipLaunchKernelGGL(fused_vec_mixed_all<TASER_PREC_F16>, grid, block, 0, s, a, m);
+    else
+      hipLaunchKernelGGL(fused_vec_mixed_all<TASER_PREC_F32>, grid, block, 0, s, a, m);
+    return hipGetLastError();
+  }
   for (int b = 0; b < kMixedBuckets; ++b) {
-    const int g = blocks ? blocks[b] : 0;
-    if (b == 0) launch_mixed_nt<1>(a, m, b, g, s);
-    if (b == 1) launch_mixed_nt<2>(a, m, b, g, s);
-    if (b == 2) launch_mixed_nt<4>(a, m, b, g, s);
+    const int g = launch ? launch->blocks[b] : 0;
+    const int w = launch ? launch->waves[b] : 0;
+    if (b == 0) launch_mixed_nt<1>(a, m, b, g, w, s);
+    if (b == 1) launch_mixed_nt<2>(a, m, b, g, w, s);
+    if (b == 2) launch_mixed_nt<4>(a, m, b, g, w, s);
   }
   return hipGetLastError();
 }

@@ -397,9 +397,13 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, cons
   if (!Bv || !Uv || !modv || !H_off || !y_off || !H || !y || !sbar || !status) return TASER_ERR_ARG;
   if (desc->tau_mode == TASER_TAU_GIVEN && !tau_in) return TASER_ERR_ARG;
   if (stride < 64) return TASER_ERR_SHAPE;
-  if (launch)
-    for (int b = 0; b < kMixedBuckets; ++b)
+  if (launch) {
+    for (int b = 0; b < kMixedBuckets; ++b) {
       if (launch->blocks[b] < 0 || launch->blocks[b] > (1 << 20)) return TASER_ERR_ARG;
+      if (launch->waves[b] != 0 && launch->waves[b] != 1) return TASER_ERR_ARG;
+    }
+    if (launch->single_launch != 0 && launch->single_launch != 1) return TASER_ERR_ARG;
+  }
   const size_t need = mixed_workspace_bytes(desc->num_vectors);
   if (!ws || ws_bytes < need) return TASER_ERR_WORKSPACE;
   FusedArgs a{};
@@ -413,7 +417,7 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, cons
   m.count = static_cast<int32_t*>(ws);
   m.list = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + 256);
   return launch_status([&] {
-    return launch_mixed(a, m, launch ? launch->blocks : nullptr, static_cast<hipStream_t>(stream));
+    return launch_mixed(a, m, launch, static_cast<hipStream_t>(stream));
   });
 }
 

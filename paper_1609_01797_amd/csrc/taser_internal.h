@@ -123,7 +123,8 @@ struct MixedArgs {
   int32_t* list;
 };
 size_t mixed_workspace_bytes(int V);
-hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const int* blocks, hipStream_t s);
+hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const taser_mixed_launch_t* launch,
+                        hipStream_t s);
 
 // Unfolded variant (per-iteration step sizes) and its adjoint.
 struct UnfoldedArgs {

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_sizes():
     lib = taser.load()
-    assert lib.taser_abi_version() == 1
+    assert lib.taser_abi_version() == 2
     assert lib.taser_problem_size(16, taser.QPSK) == 33
     assert lib.taser_problem_size(32, taser.BPSK) == 33
     assert lib.taser_problem_size(0, taser.QPSK) == -1
@@ -144,6 +144,12 @@ def test_mixed_entry_rejects_bad_arguments():
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 32, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_SHAPE
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 8, z) == taser.ERR_WORKSPACE
     launch.blocks[1] = -3
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
+    launch.blocks[1] = 0
+    launch.waves[2] = 2
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
+    launch.waves[2] = 1
+    launch.single_launch = 3
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
 
 

@@ -87,6 +87,13 @@ def test_mixed_launch_configs_agree(gpu_lib, mixed_case):
         torch.cuda.synchronize()
         for k in ("sbar", "margin", "status"):
             assert torch.equal(r[k], base[k]), (blocks, k)
+    # the alternative register budgets and the single launch over one work
+    # queue run the same arithmetic
+    for waves, single in (([1, 1, 1], False), ([1, 0, 1], False), ([0, 0, 0], True), ([1, 1, 1], True)):
+        r = gpu_lib.run_mixed(desc, *ins, want_margin=True, waves=waves, single=single)
+        torch.cuda.synchronize()
+        for k in ("sbar", "margin", "status"):
+            assert torch.equal(r[k], base[k]), (waves, single, k)
 
 
 def test_mixed_graph_capture_replay(gpu_lib, mixed_case):
