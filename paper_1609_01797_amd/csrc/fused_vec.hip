@@ -18,6 +18,7 @@
 
 #include <type_traits>
 
+#include "spectral.h"
 #include "taser_internal.h"
 
 namespace taser {
@@ -866,6 +867,69 @@ void fused_vec(FusedArgs a) {
   vec_body<NT, P>(a, job, lds);
 }
 
+// ---------------------------------------------------------------------------
+// taser_build_T for N - 1 <= 64 and U <= 32: the per-vector kernel's
+// preprocessing (complex Gram on the matrix cores) writes T~ and D, then the
+// Lanczos norm that the general preprocessing kernel uses gives ||T~||_2, so
+// lam, tau and status follow the same definitions there and here.
+template <int NT>
+__global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
+  constexpr int N1 = 16 * NT;
+  constexpr int LD = N1 + 1;
+  constexpr int NMAX = N1 + 1;
+  __shared__ __align__(16) float T[VecLds<NT>::TT];
+  __shared__ float Tr[NMAX * NMAX];
+  __shared__ float Q[spectral::kLanczosMax * NMAX];
+  __shared__ float Dl[N1 + 1];
+  __shared__ float al[spectral::kLanczosMax], be2[spectral::kLanczosMax];
+  const int lane = threadIdx.x;
+  const long long v = blockIdx.x;
+  const int N = a.N, Nm1 = N - 1;
+  const bool jed = a.mode == TASER_JED;
+  VecJob job{};
+  job.v = v;
+  job.B = a.B; job.U = a.U; job.N = N; job.mod = a.mod;
+  if (jed) {
+    job.H = nullptr;
+    job.y = a.y + v * (long long)(a.U + 1) * a.B;
+    job.s0 = a.s0[v];
+  } else {
+    job.H = a.H + (v / a.y_per_H) * (long long)a.B * a.U;
+    job.y = a.y + v * (long long)a.B;
+    job.s0 = make_float2(1.f, 0.f);
+  }
+  vec_build_T<NT, TASER_PREC_F32>(job, jed, T);
+
+  int bad = 0, deg = 0;
+  for (int e = lane; e < VecLds<NT>::TT; e += 64)
+    if (!isfinite(T[e])) bad = 1;
+  const bool nonfinite = or_all(bad);
+  for (int k = lane; k <= N1; k += 64) {
+    const bool real_k = k < Nm1 || k == N1;
+    const float d = nonfinite ? 0.f : fabsf(T[k * LD + k]);
+    if (real_k && d == 0.f) deg = 1;
+    Dl[k] = (d == 0.f || !real_k) ? 1.f : hsqrt(d);
+  }
+  const bool degenerate = !nonfinite && or_all(deg);
+  __syncthreads();
+  float* Ttg = a.Tt + v * (long long)N * N;
+  for (int e = lane; e < N * N; e += 64) {
+    const int i = e / N, j = e - i * N;
+    const int pi = i < Nm1 ? i : N1, pj = j < Nm1 ? j : N1;
+    const float t = nonfinite ? 0.f : T[pi * LD + pj] * rcp(Dl[pi] * Dl[pj]);
+    Tr[e] = t;
+    Ttg[e] = t;
+  }
+  for (int k = lane; k < N; k += 64) a.D[v * N + k] = Dl[k < Nm1 ? k : N1];
+  __syncthreads();
+  const float lam = spectral::lanczos_norm(Tr, N, a.U <= a.B, Q, al, be2);
+  if (lane == 0) {
+    a.lam[v] = lam;
+    if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);
+    a.status[v] = nonfinite ? TASER_VEC_NONFINITE : (degenerate ? TASER_VEC_DEGENERATE : 0);
+  }
+}
+
 // Mixed-size batch: a persistent grid walks the list of vectors of one size
 // bucket that the bucketing kernel left in the workspace.
 template <int NT, int P>
@@ -1092,6 +1156,23 @@ hipError_t launch_fused_vec(const FusedArgs& a, hipStream_t s) {
     case 1: launch_vec_nt<1>(a, s); break;
     case 2: launch_vec_nt<2>(a, s); break;
     case 4: launch_vec_nt<4>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int build_T_vec_tiles(const StagedArgs& a) {
+  if (a.U > 32 || a.B < 1) return 0;
+  if (a.mode == TASER_JED && a.y_per_H != 1) return 0;
+  const int nm1 = a.N - 1;
+  return nm1 <= 16 ? 1 : nm1 <= 32 ? 2 : nm1 <= 64 ? 4 : 0;
+}
+
+hipError_t launch_build_T_vec(const StagedArgs& a, hipStream_t s) {
+  switch (build_T_vec_tiles(a)) {
+    case 1: hipLaunchKernelGGL(build_T_vec<1>, dim3(a.V), dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(build_T_vec<2>, dim3(a.V), dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(build_T_vec<4>, dim3(a.V), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

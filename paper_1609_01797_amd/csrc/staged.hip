@@ -4,91 +4,21 @@
 // kernel (fused.hip) is the fast path for the power-of-two shapes.
 #include <math.h>
 
+#include "spectral.h"
 #include "taser_internal.h"
 
 namespace taser {
 namespace {
 
+using spectral::hsqrt;
+using spectral::kLanczosMax;
+using spectral::rcp;
+using spectral::rsq;
+using spectral::wave_sum;
+
 constexpr int kBuildThreads = 256;
-// Krylov dimension cap for ||T~||_2: 16 steps when U <= B (the top
-// eigenvalue stands out; float32 resolution from -4 dB up), 24 for
-// overloaded systems (U > B), whose leading eigenvalues crowd together.
-constexpr int kLanczosMax = 24;
-constexpr int kLanczosWellPosed = 16;
 constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
-
-// Sum over the 64 lanes of a wave, on the vector ALUs: rotations inside each
-// 16-lane row (DPP row_ror 8, 4, 2, 1), then the gfx950 lane swaps across
-// rows (permlane32 / permlane16: with both operands equal the two results
-// are a value and its partner's).  A shuffle-based reduction goes through
-// the LDS pipe, and the Lanczos reorthogonalisation makes hundreds of these
-// reductions one after another.
-__device__ inline float wave_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xF, 0xF, false));
-  const unsigned u = __float_as_uint(v);
-  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-  v = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-  const unsigned w = __float_as_uint(v);
-  const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Hardware reciprocal, square root and reciprocal square root (about one
-// ulp; the correctly rounded library forms cost some twenty instructions).
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// Sturm count: number of eigenvalues of the symmetric tridiagonal
-// (a[0..m-1], b[0..m-2]) that are smaller than x.
-__device__ int sturm_count(const float* a, const float* b2, int m, float x, float pivmin) {
-  int cnt = 0;
-  float d = a[0] - x;
-  if (fabsf(d) < pivmin) d = -pivmin;
-  cnt += d < 0.f;
-  for (int i = 1; i < m; ++i) {
-    d = a[i] - x - b2[i - 1] * rcp(d);
-    if (fabsf(d) < pivmin) d = -pivmin;
-    cnt += d < 0.f;
-  }
-  return cnt;
-}
-
-// Largest (want_max) or smallest eigenvalue of a tridiagonal by 65-way
-// multisection: each of the 64 lanes evaluates one interior point per round.
-__device__ float tridiag_extreme(const float* a, const float* b2, int m, float lo, float hi,
-                                 bool want_max, float pivmin) {
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int round = 0; round < 6; ++round) {
-    const float w = (hi - lo) * (1.f / 65.f);
-    const float x = lo + w * (float)(lane + 1);
-    const int c = sturm_count(a, b2, m, x, pivmin);
-    // want_max: first point with every eigenvalue below it bounds lambda_max
-    // from above; want_min: first point with at least one eigenvalue below.
-    const bool hit = want_max ? (c >= m) : (c >= 1);
-    const unsigned long long mask = __ballot(hit);
-    const int first = mask ? __ffsll((long long)mask) - 1 : kWave;
-    const float new_hi = (first < kWave) ? lo + w * (float)(first + 1) : hi;
-    const float new_lo = lo + w * (float)first;
-    lo = new_lo;
-    hi = new_hi;
-    if (!(hi - lo > 0.f)) break;
-  }
-  return 0.5f * (lo + hi);
-}
-
-// Deterministic Lanczos start vector with no structural zero component.
-__device__ inline float start_entry(int i) {
-  unsigned h = (unsigned)(i + 1) * 0x9E3779B9u;
-  h ^= h >> 15;
-  h *= 0x85EBCA6Bu;
-  h ^= h >> 13;
-  return 1.0f + (float)(h & 0xFFFFu) * (1.0f / 65536.0f);
-}
 
 // One workgroup per vector.
 //   phase 1: complex Gram G = H^H H, b = H^H y, ||y||^2 (JED: H := Y_r,
@@ -208,97 +138,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   __shared__ float al[kLanczosMax], be2[kLanczosMax];
   if (tid < kWave) {
     const int lane = tid;
-    const int m_lim = U <= B ? kLanczosWellPosed : kLanczosMax;
-    const int m_cap = N < m_lim ? N : m_lim;
-    // Start: the last column of T~ (the dominant eigenvector weighs the last
-    // coordinate heavily, so few steps reach float32 resolution) plus 1 % of
-    // a vector without structural zeros, so that an eigenvector orthogonal
-    // to that column is still in the Krylov space.  Each lane reads and
-    // writes only its own entries of Q.
-    float nc = 0.f, ns = 0.f;
-    for (int r = lane; r < N; r += kWave) {
-      const float c = T[(size_t)r * N + N - 1], s = start_entry(r);
-      nc += c * c;
-      ns += s * s;
-    }
-    nc = wave_sum(nc);
-    ns = wave_sum(ns);
-    const float ic = nc > 0.f ? rsq(nc) : 0.f, is = 1e-2f * rsq(ns);
-    float nrm = 0.f;
-    for (int r = lane; r < N; r += kWave) {
-      const float q = T[(size_t)r * N + N - 1] * ic + start_entry(r) * is;
-      Q[r] = q;
-      nrm += q * q;
-    }
-    nrm = wave_sum(nrm);
-    const float inv0 = rsq(nrm);
-    for (int r = lane; r < N; r += kWave) Q[r] *= inv0;
-    int m = 0;
-    float scale = 0.f;
-    for (int j = 0; j < m_cap; ++j) {
-      const float* q = Q + (size_t)j * N;
-      float w[3];
-      float dot = 0.f;
-      for (int s = 0; s < 3; ++s) {
-        const int r = lane + s * kWave;
-        float acc = 0.f;
-        if (r < N) {
-          // four independent partial sums so that the LDS loads of the row
-          // and of q pipeline instead of waiting one FMA at a time
-          const float* row = T + (size_t)r * N;
-          float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-          int k = 0;
-          for (; k + 4 <= N; k += 4) {
-            p0 += row[k] * q[k];
-            p1 += row[k + 1] * q[k + 1];
-            p2 += row[k + 2] * q[k + 2];
-            p3 += row[k + 3] * q[k + 3];
-          }
-          for (; k < N; ++k) p0 += row[k] * q[k];
-          acc = (p0 + p1) + (p2 + p3);
-          dot += acc * q[r];
-        }
-        w[s] = acc;
-      }
-      const float alpha_j = wave_sum(dot);
-      if (lane == 0) al[j] = alpha_j;
-      m = j + 1;
-      scale = fmaxf(scale, fabsf(alpha_j));
-      if (j == m_cap - 1) break;
-      // two passes of classical Gram-Schmidt against every Lanczos vector
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i <= j; ++i) {
-          const float* qi = Q + (size_t)i * N;
-          float c = 0.f;
-          for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) c += w[s] * qi[r]; }
-          c = wave_sum(c);
-          for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) w[s] -= c * qi[r]; }
-        }
-      }
-      float bb = 0.f;
-      for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) bb += w[s] * w[s]; }
-      bb = wave_sum(bb);
-      const float ib = bb > 0.f ? rsq(bb) : 0.f;
-      const float beta = bb * ib;          // sqrt(bb)
-      scale = fmaxf(scale, beta);
-      if (!(beta > 1e-6f * scale)) break;   // invariant subspace found
-      if (lane == 0) be2[j] = bb;
-      float* qn = Q + (size_t)(j + 1) * N;
-      for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) qn[r] = w[s] * ib; }
-      __builtin_amdgcn_wave_barrier();
-    }
-    __builtin_amdgcn_wave_barrier();
-    // Gershgorin interval of the Ritz tridiagonal
-    float lo = 3.4e38f, hi = -3.4e38f;
-    for (int i = 0; i < m; ++i) {
-      const float r = (i > 0 ? hsqrt(be2[i - 1]) : 0.f) + (i < m - 1 ? hsqrt(be2[i]) : 0.f);
-      lo = fminf(lo, al[i] - r);
-      hi = fmaxf(hi, al[i] + r);
-    }
-    const float pivmin = 1e-30f + 1e-12f * fmaxf(fabsf(lo), fabsf(hi));
-    const float emax = tridiag_extreme(al, be2, m, lo, hi, true, pivmin);
-    const float emin = tridiag_extreme(al, be2, m, lo, hi, false, pivmin);
-    const float lam = fmaxf(fabsf(emax), fabsf(emin));
+    const float lam = spectral::lanczos_norm(T, N, U <= B, Q, al, be2);
     if (lane == 0) {
       a.lam[v] = lam;
       if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);

@@ -108,12 +108,16 @@ taser_status_t taser_build_T(const taser_desc_t* desc, const void* H, const void
   if (!y || !Tt || !D || !lam || !tau || !status) return TASER_ERR_ARG;
   if (!jed && !H) return TASER_ERR_ARG;
   if (jed && !s0) return TASER_ERR_ARG;
-  if (build_T_lds_bytes(a.B, a.U, a.N) == 0) return TASER_ERR_UNSUPPORTED;
+  const bool vec = build_T_vec_tiles(a) > 0;
+  if (!vec && build_T_lds_bytes(a.B, a.U, a.N) == 0) return TASER_ERR_UNSUPPORTED;
   a.H = static_cast<const float2*>(H);
   a.y = static_cast<const float2*>(y);
   a.s0 = static_cast<const float2*>(s0);
   a.Tt = Tt; a.D = D; a.lam = lam; a.tau = tau; a.status = status;
-  return launch_status([&] { return launch_build_T(a, static_cast<hipStream_t>(stream)); });
+  return launch_status([&] {
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    return vec ? launch_build_T_vec(a, s) : launch_build_T(a, s);
+  });
 }
 
 static FixedArgs fixed_args(const taser_desc_t* d) {

@@ -26,6 +26,10 @@ struct StagedArgs {
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_build_T(const StagedArgs& a, hipStream_t s);
+// taser_build_T through the per-vector preprocessing (N - 1 <= 64, U <= 32):
+// tiles > 0 when it applies.
+int build_T_vec_tiles(const StagedArgs& a);
+hipError_t launch_build_T_vec(const StagedArgs& a, hipStream_t s);
 hipError_t launch_solve(const StagedArgs& a, const float* Tt, const float* D, const float* tau,
                         float* L, int32_t* status, hipStream_t s);
 hipError_t launch_detect(int32_t V, int32_t N, const float* L, const float* D, int8_t* sbar,
