@@ -17,23 +17,23 @@ What the paper fixes:
     2^11 words of 14 bits with 13 fraction bits, and the scale unit
     multiplies it by D_jj.
 
-Readings where the paper is silent (F1..F8, also listed in the design
+Readings where the paper is silent (Q1..Q8, also listed in the design
 notes):
-  F1 words are two's complement and saturate at [-2^13, 2^13 - 1];
-  F2 T^ = 2 tau T~ has 12 fraction bits (|T~_ij| <= 1 and tau <= 1/||T~||_2
+  Q1 words are two's complement and saturate at [-2^13, 2^13 - 1];
+  Q2 T^ = 2 tau T~ has 12 fraction bits (|T~_ij| <= 1 and tau <= 1/||T~||_2
      <= 1, so |T^_ij| < 2 fits); D_kk (k < N) has the 8 fraction bits of the
      diagonal element it initialises, D_NN the 5 of L~_NN;
-  F3 a processing element accumulates its products exactly (a wide
+  Q3 a processing element accumulates its products exactly (a wide
      accumulator) and rounds once, when V_ij is stored;
-  F4 rounding is to nearest with ties upwards: floor(x / 2^s + 1/2);
-  F5 squared column norms are exact sums, with 16 fraction bits (the bottom
+  Q4 rounding is to nearest with ties upwards: floor(x / 2^s + 1/2);
+  Q5 squared column norms are exact sums, with 16 fraction bits (the bottom
      row's 7-bit values are aligned by 2^2 before squaring);
-  F6 the table is indexed by the top 11 bits of the squared norm after a
+  Q6 the table is indexed by the top 11 bits of the squared norm after a
      shift by an even number of bits that puts its leading one in bit 10 or
      9 (so indices 512..2047 occur), and entry i holds the integer nearest
      to 2^13 / sqrt((i + 1/2) / 2^10);
-  F7 the scale factor D_jj / ||v_j|| has 11 fraction bits;
-  F8 a column whose squared norm is 0 is reset to D_jj e_j (reading R8 of
+  Q7 the scale factor D_jj / ||v_j|| has 11 fraction bits;
+  Q8 a column whose squared norm is 0 is reset to D_jj e_j (reading R8 of
      the floating-point oracle), and vectors flagged degenerate or
      non-finite by the preprocessing run no iterations.
 """
@@ -48,9 +48,9 @@ WMIN, WMAX = -(1 << (WORD_BITS - 1)), (1 << (WORD_BITS - 1)) - 1
 F_L = 8        # L~ and V, rows 1..N-1 (and D_kk, k < N)
 F_B = 7        # bottom row of L~ and V
 F_NN = 5       # L~_NN = D_NN
-F_T = 12       # T^ = 2 tau T~ (reading F2)
-F_Q = 16       # squared column norms (reading F5)
-F_C = 11       # scale factor D_jj / ||v_j|| (reading F7)
+F_T = 12       # T^ = 2 tau T~ (reading Q2)
+F_Q = 16       # squared column norms (reading Q5)
+F_C = 11       # scale factor D_jj / ||v_j|| (reading Q7)
 LUT_BITS = 11
 LUT_FRAC = 13
 
@@ -58,13 +58,13 @@ VEC_ZERO_NORM = 4
 
 
 def quantize(x, frac_bits):
-    """Real value -> 14-bit word with ``frac_bits`` fraction bits (F1, F4)."""
+    """Real value -> 14-bit word with ``frac_bits`` fraction bits (Q1, Q4)."""
     q = np.floor(np.asarray(x, dtype=np.float64) * float(1 << frac_bits) + 0.5)
     return np.clip(q, WMIN, WMAX).astype(np.int64)
 
 
 def round_shift(x, s):
-    """floor(x / 2^s + 1/2) for int64 x and s >= 1 (F4)."""
+    """floor(x / 2^s + 1/2) for int64 x and s >= 1 (Q4)."""
     return (np.asarray(x, dtype=np.int64) + (1 << (s - 1))) >> s
 
 
@@ -73,7 +73,7 @@ def saturate(x):
 
 
 def rsqrt_table():
-    """The 2^11-word inverse-square-root table (F6): entry i (i >= 512) is the
+    """The 2^11-word inverse-square-root table (Q6): entry i (i >= 512) is the
     integer nearest to 2^13 / sqrt((i + 1/2) / 2^10) = 2^18 / sqrt(i + 1/2),
     found exactly with integer arithmetic: r is nearest to sqrt(X) with
     X = 2^37 / (2i + 1) iff (2r - 1)^2 (2i + 1) <= 2^39 < (2r + 1)^2 (2i + 1)
@@ -104,7 +104,7 @@ def _lut():
 def scale_factor(q, d):
     """The scale unit (Section IV-A): D_jj / ||v_j|| with 11 fraction bits,
     from the squared norm q (> 0, 16 fraction bits) and D_jj (8 fraction
-    bits), via the table (F6, F7).  With q = idx 2^s (s even),
+    bits), via the table (Q6, Q7).  With q = idx 2^s (s even),
     1/sqrt(q 2^-16) = LUT[idx] 2^(-10 - s/2), so the factor in units of
     2^-11 is d LUT[idx] 2^(-7 - s/2)."""
     q = np.asarray(q, dtype=np.int64)
@@ -128,7 +128,7 @@ def scale_factor(q, d):
 
 
 def fixed_inputs(Tt, D, tau, product_dtype=np.float64):
-    """Quantise the preprocessing outputs (F2): T^ = 2 tau T~ with 12
+    """Quantise the preprocessing outputs (Q2): T^ = 2 tau T~ with 12
     fraction bits; D_kk with 8 (k < N) and D_NN with 5 fraction bits.
     ``product_dtype`` is the precision in which 2 tau T~ is formed before
     rounding to a word: float64 here, float32 to take the same decision as a
@@ -152,11 +152,11 @@ def fixed_iterate(That, d, t_max, skip=None):
     5-bit register value), and status bits (VEC_ZERO_NORM).
 
     Each iteration, for every element j <= i of row i (row format F):
-        acc   = L_ij 2^12 - sum_{k <= i} L_ik T^_kj      (exact, F3)
+        acc   = L_ij 2^12 - sum_{k <= i} L_ik T^_kj      (exact, Q3)
         V_ij  = sat(round(acc / 2^12))                  (F fraction bits)
     then for every column j < N the squared norm
-        q_j = sum_{i < N} V_ij^2 + 4 V_Nj^2             (16 fraction bits, F5)
-    and, with the scale unit's c_j (F6, F7),
+        q_j = sum_{i < N} V_ij^2 + 4 V_Nj^2             (16 fraction bits, Q5)
+    and, with the scale unit's c_j (Q6, Q7),
         L_ij = sat(round(V_ij c_j / 2^11))              (same row format)
     while L~_NN keeps its 5-bit value (Section IV-C)."""
     That = np.asarray(That, dtype=np.int64)

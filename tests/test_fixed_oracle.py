@@ -60,7 +60,7 @@ def test_scale_unit_exact_cases(q, d, expect):
 
 
 def test_saturation():
-    """A V that leaves the 14-bit range is clamped (reading F1): with
+    """A V that leaves the 14-bit range is clamped (reading Q1): with
     D_11 = 8191 (31.996) and T^_11 = -2.0, V_11 = D_11 (1 + 2) = 24573 > 8191
     becomes 8191; the column then has norm 8191 (bottom row 0), the scale
     factor is round(8191 * table / 2^(7 + s/2)) for q = 8191^2 and the new
@@ -111,7 +111,7 @@ def test_tracks_the_floating_point_oracle(B, U, snr, alpha):
 
 
 def test_degenerate_vectors_skip_and_zero_norm_reset():
-    """Skipped vectors keep L~ = D (reading F8); a column whose V is zero is
+    """Skipped vectors keep L~ = D (reading Q8); a column whose V is zero is
     reset to D_jj e_j and flagged."""
     T = np.zeros((2, 3, 3), dtype=np.int64)
     T[:, 0, 0] = 4096          # 2 tau T~_11 = 1: V_11 = D_11 (1 - 1) = 0, column 1 of V is zero
