@@ -189,7 +189,7 @@ taser_status_t taser_reference_detect(const taser_desc_t* desc, int32_t kind, in
    diag(S) = 1 and S positive semidefinite, then (Section II-C) the signs
    of the leading eigenvector of S^, oriented so that its last entry (the
    fixed entry of s~) is non-negative; sign(0) = +1.  Both modes, 2 <= N <=
-   64 (desc: mode, B, U, mod, num_vectors as for taser_build_T; t_max,
+   65 (desc: mode, B, U, mod, num_vectors as for taser_build_T; t_max,
    prec, tau_mode, alpha unused).  Solved per vector in float64 by a
    primal-dual interior-point method (HKM direction, adaptive centring,
    backtracked steps at 0.95 of the boundary) until the duality gap is
@@ -205,7 +205,7 @@ taser_status_t taser_reference_detect(const taser_desc_t* desc, int32_t kind, in
        T), X [V][N][N] (the final primal iterate), all float64;
        iterations [V].
    Errors: those of taser_check_desc, TASER_ERR_ARG (NULL Tt or sbar with
-   V > 0), TASER_ERR_UNSUPPORTED (N > 64). */
+   V > 0), TASER_ERR_UNSUPPORTED (N > 65). */
 taser_status_t taser_sdr_detect(const taser_desc_t* desc, const float* Tt, const float* D,
                                 const int32_t* status, int8_t* sbar, double* objective, double* gap,
                                 double* X, int32_t* iterations, void* stream);

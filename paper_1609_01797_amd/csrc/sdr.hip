@@ -1,12 +1,12 @@
 // Exact semidefinite relaxation (eq. (7)): min Tr(T S) subject to
 // diag(S) = 1 and S positive semidefinite, then the signs of the leading
-// eigenvector of S (Section II-C), for 2 <= N <= 64, in float64 (the
+// eigenvector of S (Section II-C), for 2 <= N <= 65, in float64 (the
 // vector units run it at the float32 rate, and the interior-point iterates
 // need the resolution: near the optimum X is close to rank one).
 //
-// One wave per problem; its matrices live in LDS (odd row stride, so that a
-// lane-per-row access spreads over the banks) and lane i owns row or
-// column i.  A primal-dual interior-point method with the HKM direction
+// One workgroup per problem (one wave for N <= 64, two for N = 65); its
+// matrices live in LDS (odd row stride, so that a lane-per-row access
+// spreads over the banks) and thread i owns row or column i.  A primal-dual interior-point method with the HKM direction
 // keeps X (diag(X) = 1) and y (Z = C - Diag(y) positive definite) feasible,
 // with C = T / max|T_ij| (the argmin does not change).  Each iteration, with
 // mu = <X, Z> / N and a target sigma mu on the central path (sigma = 0.5 at
@@ -50,20 +50,56 @@ struct SdrLds {
   real A[NP * LD];   // Cholesky of Z, Zinv, dX (symmetrised), X powers
   real B[NP * LD];   // L^-1, Schur matrix, dX (unsymmetrised), step trials, X powers
   real v[NP];
+  real red[2];       // per-wave partials of block reductions (two waves)
   int ok;
 };
+
+template <int NP>
+constexpr int kThreads = NP <= 64 ? 64 : 128;
 
 __device__ real wave_sum(real x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
 
+// Sum (or maximum) over the workgroup, called by every thread at the same
+// point; with two waves the partials meet in LDS between two barriers.
+template <int NP>
+__device__ real block_sum(real x, real* red) {
+  x = wave_sum(x);
+  if constexpr (kThreads<NP> == 64) {
+    return x;
+  } else {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return red[0] + red[1];
+  }
+}
+
+template <int NP>
+__device__ real block_max(real x, real* red) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  if constexpr (kThreads<NP> == 64) {
+    return x;
+  } else {
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return fmax(red[0], red[1]);
+  }
+}
+
 // In-place Cholesky of the leading N x N block (lower triangle); false when
 // a pivot is not positive and finite.  Entries above the diagonal are left
 // as they were.
-template <int LD>
+// With two waves the column of L must be complete before the update reads
+// it (one wave executes its LDS accesses in program order and needs no
+// barrier there).
+template <int LD, bool kTwoWaves>
 __device__ bool chol(real* A, int N, int* ok) {
   const int i = threadIdx.x;
+  __syncthreads();  // every thread has read the previous result
   if (i == 0) *ok = 1;
   __syncthreads();
   for (int k = 0; k < N; ++k) {
@@ -74,19 +110,22 @@ __device__ bool chol(real* A, int N, int* ok) {
       A[k * LD + k] = good ? sqrt(d) : 1.0;
     }
     __syncthreads();
+    real lik = 0.0;
     if (i > k && i < N) {
-      const real lik = A[i * LD + k] / A[k * LD + k];
+      lik = A[i * LD + k] / A[k * LD + k];
       A[i * LD + k] = lik;
-      for (int j = k + 1; j <= i; ++j) A[i * LD + j] -= lik * A[j * LD + k];
     }
+    if constexpr (kTwoWaves) __syncthreads();
+    if (i > k && i < N)
+      for (int j = k + 1; j <= i; ++j) A[i * LD + j] -= lik * A[j * LD + k];
     __syncthreads();
   }
   return *ok != 0;
 }
 
-// dst = src * src / trace(src * src), row i in lane i.
-template <int LD>
-__device__ void square_normalised(const real* src, real* dst, int N) {
+// dst = src * src / trace(src * src), row i in thread i.
+template <int NP, int LD>
+__device__ void square_normalised(const real* src, real* dst, int N, real* red) {
   const int i = threadIdx.x;
   real diag = 0.0;
   if (i < N)
@@ -96,7 +135,7 @@ __device__ void square_normalised(const real* src, real* dst, int N) {
       dst[i * LD + j] = acc;
       if (j == i) diag = acc;
     }
-  const real tr = wave_sum(diag);
+  const real tr = block_sum<NP>(diag, red);
   const real inv = tr > 0.0 && isfinite(tr) ? 1.0 / tr : 0.0;
   if (i < N)
     for (int j = 0; j < N; ++j) dst[i * LD + j] *= inv;
@@ -104,7 +143,7 @@ __device__ void square_normalised(const real* src, real* dst, int N) {
 }
 
 template <int NP>
-__global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
+__global__ __launch_bounds__(kThreads<NP>) void sdr_kernel(SdrArgs a) {
   constexpr int LD = SdrLds<NP>::LD;
   __shared__ SdrLds<NP> s;
   const int i = threadIdx.x;
@@ -127,7 +166,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
       mx = fmax(mx, fabs(t));
     }
   }
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  mx = block_max<NP>(mx, s.red);
   const bool run = !skip && mx > 0.0 && isfinite(mx);
   const real scale = run ? mx : 1.0;
   const real iscale = 1.0 / scale;
@@ -156,8 +195,8 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
         xz += s.X[i * LD + j] * z;
         cx += s.X[i * LD + j] * s.C[i * LD + j];
       }
-    xz = wave_sum(xz);
-    cx = wave_sum(cx);
+    xz = block_sum<NP>(xz, s.red);
+    cx = block_sum<NP>(cx, s.red);
     const real ref = fmax(1.0, fabs(cx));
     if (xz <= kGapTol * ref) break;
     real old = hist[0];
@@ -167,7 +206,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
     if (xz <= kStallTol * ref && !(xz < 0.5 * old)) break;  // stalled at the rounding floor
     const real smu = sigma * xz / (real)N;
     __syncthreads();
-    if (!chol<LD>(s.A, N, &s.ok)) break;
+    if (!chol<LD, (kThreads<NP> > 64)>(s.A, N, &s.ok)) break;
     // B = L^-1 (lower triangular): lane i forward-substitutes column i
     if (row)
       for (int r = 0; r < N; ++r) {
@@ -190,7 +229,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
       s.v[i] = 1.0 - smu * s.A[i * LD + i];
     }
     __syncthreads();
-    if (!chol<LD>(s.B, N, &s.ok)) break;
+    if (!chol<LD, (kThreads<NP> > 64)>(s.B, N, &s.ok)) break;
     for (int k = 0; k < N; ++k) {
       if (i == k) s.v[k] /= s.B[k * LD + k];
       __syncthreads();
@@ -224,7 +263,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
       if (row)
         for (int j = 0; j < N; ++j) s.B[i * LD + j] = s.X[i * LD + j] + ap * s.A[i * LD + j];
       __syncthreads();
-      okp = chol<LD>(s.B, N, &s.ok);
+      okp = chol<LD, (kThreads<NP> > 64)>(s.B, N, &s.ok);
       if (!okp) ap *= 0.8;
     }
     real ad = 1.0;
@@ -234,7 +273,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
         for (int j = 0; j < N; ++j)
           s.B[i * LD + j] = s.C[i * LD + j] - (i == j ? yi + ad * dyi : 0.0);
       __syncthreads();
-      okd = chol<LD>(s.B, N, &s.ok);
+      okd = chol<LD, (kThreads<NP> > 64)>(s.B, N, &s.ok);
       if (!okd) ad *= 0.8;
     }
     if (!okp && !okd) break;
@@ -251,8 +290,9 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
 
   // leading eigenvector: X^32 (trace-normalised), then power iteration on
   // it from the last column of X
-  square_normalised<LD>(s.X, s.A, N);
-  for (int q = 1; q < kSquarings; ++q) square_normalised<LD>(q & 1 ? s.A : s.B, q & 1 ? s.B : s.A, N);
+  square_normalised<NP, LD>(s.X, s.A, N, s.red);
+  for (int q = 1; q < kSquarings; ++q)
+    square_normalised<NP, LD>(q & 1 ? s.A : s.B, q & 1 ? s.B : s.A, N, s.red);
   const real* P = (kSquarings & 1) ? s.A : s.B;
   real u = row ? s.X[i * LD + N - 1] : 0.0;
   for (int p = 0; p < kPowerIters; ++p) {
@@ -261,7 +301,7 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
     real w = 0.0;
     if (row)
       for (int j = 0; j < N; ++j) w += P[i * LD + j] * s.v[j];
-    const real nrm = wave_sum(w * w);
+    const real nrm = block_sum<NP>(w * w, s.red);
     u = nrm > 0.0 && isfinite(nrm) ? w / sqrt(nrm) : u;
     __syncthreads();
   }
@@ -273,8 +313,8 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
   real cx = 0.0;
   if (row)
     for (int j = 0; j < N; ++j) cx += s.X[i * LD + j] * s.C[i * LD + j];
-  cx = wave_sum(cx);
-  const real ysum = wave_sum(row ? yi : 0.0);
+  cx = block_sum<NP>(cx, s.red);
+  const real ysum = block_sum<NP>(row ? yi : 0.0, s.red);
   if (i == 0) {
     if (a.objective) a.objective[vec] = run ? cx * scale : 0.0;
     if (a.gap) a.gap[vec] = run ? (cx - ysum) * scale : 0.0;
@@ -288,9 +328,11 @@ __global__ __launch_bounds__(64) void sdr_kernel(SdrArgs a) {
 
 hipError_t launch_sdr(const SdrArgs& a, hipStream_t s) {
   if (a.N <= 33)
-    hipLaunchKernelGGL(sdr_kernel<33>, dim3(a.V), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(sdr_kernel<33>, dim3(a.V), dim3(kThreads<33>), 0, s, a);
+  else if (a.N <= 64)
+    hipLaunchKernelGGL(sdr_kernel<64>, dim3(a.V), dim3(kThreads<64>), 0, s, a);
   else
-    hipLaunchKernelGGL(sdr_kernel<64>, dim3(a.V), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(sdr_kernel<65>, dim3(a.V), dim3(kThreads<65>), 0, s, a);
   return hipGetLastError();
 }
 

@@ -212,7 +212,7 @@ taser_status_t taser_sdr_detect(const taser_desc_t* desc, const float* Tt, const
   taser_status_t st = check(desc);
   if (st != TASER_OK) return st;
   const int N = taser_problem_size(desc->U, desc->mod);
-  if (N > 64) return TASER_ERR_UNSUPPORTED;
+  if (N > 65) return TASER_ERR_UNSUPPORTED;
   if (desc->num_vectors == 0) return TASER_OK;
   if (!Tt || !sbar) return TASER_ERR_ARG;
   SdrArgs r{};

@@ -99,7 +99,7 @@ struct RefArgs {
 };
 hipError_t launch_reference(const RefArgs& a, hipStream_t s);
 
-// Exact SDR of eq. (7) in float64, one wave per vector, 2 <= N <= 64.
+// Exact SDR of eq. (7) in float64, one workgroup per vector, 2 <= N <= 65.
 struct SdrArgs {
   int32_t V, N;
   const float* Tt;          // [V][N][N]

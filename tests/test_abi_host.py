@@ -357,8 +357,8 @@ def test_sdr_detect_rejects_before_any_launch():
     z, one = ctypes.c_void_p(0), ctypes.c_void_p(16)
     call = lambda desc, Tt=one, sb=one: lib.taser_sdr_detect(  # noqa: E731
         ctypes.byref(desc), Tt, None, None, sb, None, None, None, None, z)
-    assert call(taser.make_desc(4, 64, 32, taser.QPSK)) == taser.ERR_UNSUPPORTED   # N = 65
-    assert call(taser.make_desc(4, 64, 64, taser.BPSK)) == taser.ERR_UNSUPPORTED   # N = 65
+    assert call(taser.make_desc(4, 64, 33, taser.QPSK)) == taser.ERR_UNSUPPORTED   # N = 67
+    assert call(taser.make_desc(4, 64, 65, taser.BPSK)) == taser.ERR_UNSUPPORTED   # N = 66
     assert call(taser.make_desc(0, 16, 8, taser.QPSK), Tt=z, sb=z) == taser.OK
     assert call(taser.make_desc(2, 16, 8, taser.QPSK), Tt=z) == taser.ERR_ARG
     assert call(taser.make_desc(2, 16, 8, taser.QPSK), sb=z) == taser.ERR_ARG

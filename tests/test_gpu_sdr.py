@@ -92,11 +92,13 @@ def test_two_by_two_closed_form(gpu_lib):
 @pytest.mark.parametrize("B, U, mod, snr", [(8, 3, oracle.QPSK, 0.0), (12, 5, oracle.QPSK, 4.0),
                                             (16, 8, oracle.QPSK, 4.0), (32, 16, oracle.BPSK, 0.0),
                                             (64, 16, oracle.QPSK, 2.0), (32, 32, oracle.BPSK, 8.0),
-                                            (128, 63, oracle.BPSK, 6.0)])
+                                            (128, 63, oracle.BPSK, 6.0), (32, 32, oracle.QPSK, 10.0),
+                                            (128, 64, oracle.BPSK, 6.0)])
 def test_sdr_given_T(gpu_lib, B, U, mod, snr):
     """T of eq. (2) from the oracle, rounded once to float32 (an input error
     of at most u sum|T_ij|); sizes from N = 7 to the largest supported,
-    N = 64, across both LDS tile sizes (N <= 33 and N <= 64)."""
+    N = 65, across the three workgroup shapes (N <= 33 and N <= 64 in one
+    wave, N = 65 in two)."""
     V = 24 if U < 32 else 8
     d = sim.gen_mimo(B, U, mod, V, 1, snr, sim.seed_for(1, snr_index=130, shard=B + U))
     T = oracle.build_T_coherent(d["H"], d["y"], mod)
