@@ -47,6 +47,8 @@ ALPHA = alpha_star("coherent128x16")   # oracle sweep, tests/golden/alpha_star.j
 SNR_TIMED = 10.0
 SNR_SWEEP = [-4.0, -2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0, 14.0, 16.0, 18.0, 20.0]
 SNR_ORACLE = [-4.0, -2.0, 0.0, 2.0, 4.0, 10.0]      # errors vanish above 4 dB at this size
+ONE_CORE_SAMPLE = 4096                               # vectors of the single-core oracle leg
+VER_REF = 1e-2                                       # the paper's criterion (Section V-A)
 BER_REF = 1e-3
 PEAK = {"mfma_fp32": 157.3, "alu_fp32": 157.3, "hbm": 8000.0}   # TFLOP/s, GB/s (MI355X datasheet)
 PRECS = (("bf16", 1), ("fp32", 0), ("fp16", 2))
@@ -173,11 +175,44 @@ def cpu_baseline(data, workdir):
             os.remove(Hpath)
             os.remove(ypath)
     n = V * len(SNR_ORACLE)
+    # one core: the same oracle in this process, BLAS limited to one thread,
+    # on the first ONE_CORE_SAMPLE vectors of the timed SNR point
+    from threadpoolctl import threadpool_limits
+    import oracle
+    d = data[SNR_ORACLE[-1]]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.detect_coherent(np.repeat(d["H"][:ONE_CORE_SAMPLE // Y_PER_H], Y_PER_H, axis=0),
+                               d["y"][:ONE_CORE_SAMPLE], MOD, alpha=ALPHA, t_max=T_MAX)
+        t1 = time.perf_counter() - t0
     return {"value": n / total, "unit": "vectors/s", "cores": cores, "kind": "oracle",
             "seconds": total,
             "sample": f"{len(SNR_ORACLE)} SNR points x {V} vectors of the workload "
                       f"(SNR dB {SNR_ORACLE}), FP64 numpy oracle with LAPACK eigvalsh for tau, "
-                      f"{cores} single-threaded worker processes"}, decisions, L_ref
+                      f"{cores} single-threaded worker processes",
+            "single_core": {"value": ONE_CORE_SAMPLE / t1, "unit": "vectors/s", "cores": 1,
+                            "sample": f"{ONE_CORE_SAMPLE} vectors at {SNR_ORACLE[-1]} dB, one process, "
+                                      "BLAS limited to one thread"},
+            "host": host_info()}, decisions, L_ref
+
+
+def host_info():
+    """The CPU the baseline ran on: model name, logical CPUs of the host and
+    the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_allowed": allowed}
 
 
 def snr_at(snrs, bers, target):
@@ -211,12 +246,14 @@ def main():
     ap.add_argument("--no-ber", action="store_true", help="skip the SNR sweep")
     ap.add_argument("--workload", default="coherent128x16",
                     choices=["coherent128x16", "jed16x16", "coherent32x8", "mixed", "unfolded64x16",
-                             "fixed128x16"],
+                             "fixed128x16", "detectors"],
                     help="coherent128x16 (default, the headline), jed16x16 (joint channel "
                          "estimation and detection, 262,144 blocks), coherent32x8 (1,000 vectors), "
                          "mixed (100,000 vectors over six (B, U, modulation) classes in one call), "
                          "unfolded64x16 (learned step sizes: training steps/s and BER vs depth), "
-                         "fixed128x16 (14-bit fixed-point mode: VER gap vs FP64 and solve time)")
+                         "fixed128x16 (14-bit fixed-point mode: VER gap vs FP64 and solve time), "
+                         "detectors (TASER against MF, MMSE, K-best, ML and exact SDR on the paper's "
+                         "128x8, 64x16 and 32x32 systems: VER, SNR at 1%% VER, SDR rank-one rate)")
     ap.add_argument("--counters", action="store_true",
                     help="run each calibration kernel once and one headline step per product "
                          "precision, then exit (the launches a --pmc counter pass reads)")
@@ -283,6 +320,7 @@ def main():
 
     # ---------------- accuracy sweep (paired inputs) ----------------
     ber = {name: [] for name, _ in PRECS}
+    ver = {name: [] for name, _ in PRECS}
     flips = {name: {} for name, _ in PRECS}
     L_err = {name: {} for name, _ in PRECS}
     tri_r, tri_c = np.tril_indices(N)
@@ -297,6 +335,7 @@ def main():
             res = taser.run(desc, H, y, want_L=want_L)
             sb = res["sbar"].cpu().numpy()
             ber[name].append(float(np.mean(sb != truth)))
+            ver[name].append(float(np.mean(np.any(sb != truth, axis=1))))
             if snr in oracle_sbar:
                 flips[name][str(snr)] = int(np.count_nonzero(sb != oracle_sbar[snr]))
             if want_L:
@@ -311,6 +350,8 @@ def main():
                                          "median": float(np.median(e))}
                 del res
     ber_fp64 = ([float(np.mean(oracle_sbar[s] != sbar_of(data[s]["s"]))) for s in SNR_ORACLE]
+                if oracle_sbar else [])
+    ver_fp64 = ([float(np.mean(np.any(oracle_sbar[s] != sbar_of(data[s]["s"]), axis=1))) for s in SNR_ORACLE]
                 if oracle_sbar else [])
 
     # ---------------- throughput at the timed SNR ----------------
@@ -434,8 +475,8 @@ def main():
     fp32["whole_step_frac_fp32_peak"] = fp32["whole_step_tflops"] / PEAK["mfma_fp32"]
     fp32["roofline_solve"] = fp32_roof
 
-    accuracy = {"snr_db": snrs, "ber": ber, "bits_per_point": V * (N - 1),
-                "paired_bit_flips_vs_fp64": flips}
+    accuracy = {"snr_db": snrs, "ber": ber, "ver": ver, "bits_per_point": V * (N - 1),
+                "vectors_per_point": V, "paired_bit_flips_vs_fp64": flips}
     if any(L_err.values()):
         accuracy["L_rel_err_vs_fp64"] = {"vectors": L_SAMPLE, "per_precision": L_err}
     if ber_fp64:
@@ -449,6 +490,15 @@ def main():
             gaps[name] = None if (s64 is None or sp is None) else sp - s64
         accuracy["ber_gap_db_at_1e-3"] = gaps
         accuracy["fp64_snr_db_at_1e-3"] = s64
+        accuracy["ver"]["fp64"] = ver_fp64
+        v64 = snr_at(SNR_ORACLE, ver_fp64, VER_REF)
+        vgaps = {}
+        for name, _ in PRECS:
+            idx = [snrs.index(s) for s in SNR_ORACLE]
+            sp = snr_at(SNR_ORACLE, [ver[name][i] for i in idx], VER_REF)
+            vgaps[name] = None if (v64 is None or sp is None) else sp - v64
+        accuracy["ver_gap_db_at_1e-2"] = vgaps
+        accuracy["fp64_snr_db_at_ver_1e-2"] = v64
 
     rec = {
         "metric": METRIC,

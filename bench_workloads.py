@@ -7,7 +7,9 @@ the launch stream, paired BER against the FP64 oracle on a sample.
 """
 from __future__ import annotations
 
+import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -238,6 +240,10 @@ def run_unfolded_workload(args):
         if timed:
             k_fwd.append(e)
     ms_step = _time(lambda: step(0), args.steps, args.warmup, stream)
+    bd = sim.gen_training_batch_torch(B, U, mod, batch, 4.0, 16.0, sim.seed_for(4, 0, 0), dev)
+    bdesc = taser.make_desc(batch, B, U, mod, t_max=1, alpha=0.5)
+    ms_build = _time(lambda: taser.build_T(bdesc, bd["H"].contiguous(), bd["y"].contiguous()),
+                     args.steps, args.warmup, stream)
     for i in range(5):
         step(i, timed=True)
     torch.cuda.synchronize()
@@ -255,7 +261,13 @@ def run_unfolded_workload(args):
     snrs = list(range(4, 17, 2))
     ber = {f"plain_t{t}": [] for t in (10, 20)}
     ber.update({f"learned_t{d}": [] for d in learned})
+    # paired comparison on the same bits (McNemar): b = learned wrong and
+    # plain right, c = the reverse; z = (b - c) / sqrt(b + c)
+    pairs = {"learned_t10_vs_plain_t20": ("learned_t10", "plain_t20"),
+             "learned_t5_vs_plain_t10": ("learned_t5", "plain_t10")}
+    paired = {k: [] for k in pairs}
     for si, snr in enumerate(snrs):
+        wrong = {}
         d = sim.gen_training_batch_torch(B, U, mod, 65536, float(snr), float(snr),
                                          sim.seed_for(4, 2 + si, 0), dev)
         Tt, D, lam, sbar = prep(d)
@@ -263,12 +275,19 @@ def run_unfolded_workload(args):
         for t in (10, 20):
             desc = taser.make_desc(65536, B, U, mod, t_max=t, alpha=alpha0)
             r = taser.run(desc, d["H"].contiguous(), d["y"].contiguous())
-            ber[f"plain_t{t}"].append(float((r["sbar"] != truth).float().mean()))
+            wrong[f"plain_t{t}"] = r["sbar"] != truth
+            ber[f"plain_t{t}"].append(float(wrong[f"plain_t{t}"].float().mean()))
         for dep, a in learned.items():
             with torch.no_grad():
                 L = unf.unfolded(a, Tt, D, lam)
             dec = torch.where(unf.last_row(L, N) >= 0, 1, -1).to(torch.int8)
-            ber[f"learned_t{dep}"].append(float((dec != truth).float().mean()))
+            wrong[f"learned_t{dep}"] = dec != truth
+            ber[f"learned_t{dep}"].append(float(wrong[f"learned_t{dep}"].float().mean()))
+        for k, (x, y_) in pairs.items():
+            b = int((wrong[x] & ~wrong[y_]).sum())
+            c = int((wrong[y_] & ~wrong[x]).sum())
+            paired[k].append({"snr_db": snr, "b": b, "c": c,
+                              "z": (b - c) / math.sqrt(b + c) if b + c else 0.0})
 
     def smallest_depth(ref):
         for dep in sorted(learned):
@@ -312,7 +331,9 @@ def run_unfolded_workload(args):
                              "learned_alpha": {d: a.cpu().tolist() for d, a in learned.items()},
                              "train_seconds": train_s,
                              "smallest_depth_matching_plain_t20": smallest_depth("plain_t20"),
-                             "smallest_depth_matching_plain_t10": smallest_depth("plain_t10")}}
+                             "smallest_depth_matching_plain_t10": smallest_depth("plain_t10"),
+                             "paired_mcnemar": paired},
+            "build_T_ms": ms_build}
 
 
 def _ver_gap(snrs, ver_ref, ver, target):
@@ -418,6 +439,151 @@ def run_fixed_workload(args):
                              f"{cores} single-threaded worker processes"}}
 
 
+def _truth(s, mod):
+    """Transmitted symbols in the order of s~: [Re; Im] (QPSK) or Re (BPSK)."""
+    s = np.asarray(s)
+    return (np.concatenate([s.real, s.imag], axis=1) if mod == 2 else s.real).astype(np.int8)
+
+
+def _cross(snrs, v, target):
+    """SNR where an error-rate curve falls through ``target`` (log-linear
+    interpolation), or None when it is not bracketed."""
+    for (s0, b0), (s1, b1) in zip(zip(snrs, v), zip(snrs[1:], v[1:])):
+        if b0 >= target > b1 and b1 > 0:
+            l0, l1, lt = np.log10(b0), np.log10(b1), np.log10(target)
+            return s0 + (s1 - s0) * (l0 - lt) / (l0 - l1)
+    return None
+
+
+def run_detectors_workload(args):
+    """The detectors of Section V-A on the paper's coherent systems (128x8,
+    64x16, 32x32; BPSK and QPSK; i.i.d. Rayleigh): vector error rates of
+    TASER (float32 and BF16 products, t_max = 10; float32 at 30 and 100),
+    the matched filter, linear MMSE, K-best (K = 5), exhaustive ML (M <= 16)
+    and exact SDR, 4,096 vectors per SNR point, every detector on the same
+    vectors; the SNR each needs for 1 % VER and its gap to exact SDR and to
+    ML; the rank-one rate of the SDR solutions; and each detector's
+    throughput on one batch.  Joint detection (B = 16, 16 + 1 slots, BPSK
+    and QPSK, t_max = 20) adds TASER against exact SDR in BER."""
+    import torch
+    import paper_1609_01797_amd as taser
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    V = 4096
+    alpha = alpha_star("coherent128x16")
+    snrs = [float(x) for x in range(-12, 25, 2)]
+    systems = [(128, 8), (64, 16), (32, 32)]
+    out = {}
+    timing_snr = 10.0
+    for B, U in systems:
+        for mod in (1, 2):
+            N = 2 * U + 1 if mod == 2 else U + 1
+            M = N - 1
+            name = f"{B}x{U}_{'qpsk' if mod == 2 else 'bpsk'}"
+            dets = ["taser_fp32_t10", "taser_bf16_t10", "taser_fp32_t30", "taser_fp32_t100", "mf", "mmse",
+                    "kbest5"]
+            if M <= 16:
+                dets.append("ml")
+            if N <= 65:
+                dets.append("sdr")
+            ver = {k: [] for k in dets}
+            rank1 = []
+            ms = {}
+            for i, snr in enumerate(snrs):
+                d = sim.gen_mimo(B, U, mod, V, 1, snr, sim.seed_for(6, snr_index=i, shard=B + U + mod))
+                truth = torch.from_numpy(_truth(d["s"], mod)).to(dev)
+                H, y = torch.from_numpy(d["H"]).to(dev), torch.from_numpy(d["y"]).to(dev)
+                calls = {}
+                for k in dets:
+                    if k.startswith("taser"):
+                        prec = taser.PREC_BF16 if "bf16" in k else taser.PREC_F32
+                        desc = taser.make_desc(V, B, U, mod, prec=prec, t_max=int(k.split("_t")[1]), alpha=alpha)
+                        calls[k] = (lambda desc=desc: taser.run(desc, H, y)["sbar"])
+                    elif k == "sdr":
+                        desc = taser.make_desc(V, B, U, mod)
+
+                        def sdr_call(desc=desc, keep=None):
+                            bt = taser.build_T(desc, H, y)
+                            r = taser.sdr_detect(desc, bt["Tt"], bt["D"], bt["status"], want_X=keep is not None)
+                            if keep is not None:
+                                keep.update(r)
+                            return r["sbar"]
+                        calls[k] = sdr_call
+                    else:
+                        kind = {"mf": taser.REF_MF, "mmse": taser.REF_MMSE, "kbest5": taser.REF_KBEST,
+                                "ml": taser.REF_ML}[k]
+                        desc = taser.make_desc(V, B, U, mod)
+                        calls[k] = (lambda desc=desc, kind=kind: taser.reference_detect(
+                            desc, kind, H, y, K=5, n0=float(d["N0"]))[0])
+                for k, fn in calls.items():
+                    if k == "sdr":
+                        keep = {}
+                        sb = calls[k](keep=keep)
+                        w = torch.linalg.eigvalsh(keep["X"])
+                        rank1.append(float((w[:, -2] <= 1e-3 * w[:, -1]).double().mean()))
+                    else:
+                        sb = fn()
+                    ver[k].append(float((sb != truth).any(dim=1).double().mean()))
+                    if snr == timing_snr:
+                        ms[k] = _time(fn, 3, 1, stream)
+            at = {k: _cross(snrs, v, 1e-2) for k, v in ver.items()}
+            ref_sdr, ref_ml = at.get("sdr"), at.get("ml")
+            out[name] = {"B": B, "U": U, "N": N, "snr_db": snrs, "ver": ver, "snr_at_1pct_ver": at,
+                         "gap_to_sdr_db": {k: (None if a is None or ref_sdr is None else a - ref_sdr)
+                                           for k, a in at.items()},
+                         "gap_to_ml_db": {k: (None if a is None or ref_ml is None else a - ref_ml)
+                                          for k, a in at.items()},
+                         "sdr_rank1_rate": rank1 if rank1 else None,
+                         "ms_per_4096_at_10db": ms,
+                         "vectors_per_s_at_10db": {k: V / (t * 1e-3) for k, t in ms.items()}}
+            print(name, {k: (None if a is None else round(a, 2)) for k, a in at.items()}, file=sys.stderr,
+                  flush=True)
+    # joint detection: TASER against exact SDR, BER, 4,096 blocks per point
+    jed = {}
+    for mod in (1, 2):
+        jsnrs = [float(x) for x in (range(-14, 1) if mod == 1 else range(-10, 5))]
+        name = f"jed16x16_{'qpsk' if mod == 2 else 'bpsk'}"
+        ber = {"taser_fp32_t20": [], "taser_bf16_t20": [], "sdr": []}
+        for i, snr in enumerate(jsnrs):
+            d = sim.gen_jed(16, 16, mod, V, snr, sim.seed_for(7, snr_index=i, shard=mod))
+            truth = torch.from_numpy(_truth(d["s"][:, 1:], mod)).to(dev)
+            Y, s0 = torch.from_numpy(d["Y"]).to(dev), torch.from_numpy(d["s0"]).to(dev)
+            for k in ber:
+                if k == "sdr":
+                    desc = taser.make_desc(V, 16, 16, mod, mode=taser.JED)
+                    bt = taser.build_T(desc, None, Y, s0)
+                    sb = taser.sdr_detect(desc, bt["Tt"], bt["D"], bt["status"])["sbar"]
+                else:
+                    prec = taser.PREC_BF16 if "bf16" in k else taser.PREC_F32
+                    desc = taser.make_desc(V, 16, 16, mod, mode=taser.JED, prec=prec, t_max=20,
+                                           alpha=alpha_star("jed16x16"))
+                    sb = taser.run(desc, None, Y, s0)["sbar"]
+                ber[k].append(float((sb != truth).double().mean()))
+        jed[name] = {"snr_db": jsnrs, "ber": ber,
+                     "gap_to_sdr_db_at_ber_1e-3": {k: _ver_gap(jsnrs, ber["sdr"], v, 1e-3) for k, v in ber.items()}}
+    # CPU leg: the float64 SDR oracle on a bounded sample of 64x16 QPSK
+    import oracle
+    from oracle import sdr as osdr
+    d = sim.gen_mimo(64, 16, 2, 64, 1, timing_snr, sim.seed_for(6, snr_index=99))
+    T = oracle.build_T_coherent(d["H"], d["y"], 2)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        osdr.sdr_detect(T)
+        cpu_s = time.perf_counter() - t0
+    key = "32x32_bpsk"
+    gap = out[key]["gap_to_sdr_db"].get("taser_fp32_t10")
+    return {"metric": "TASER (float32, t_max=10) SNR gap to exact SDR at 1% VER @32x32 BPSK",
+            "value": gap, "unit": "dB", "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32/bf16 (TASER), f32 (references), f64 (SDR)",
+            "data": "synthetic",
+            "config": {"workload": "detectors", "systems": [f"{b}x{u}" for b, u in systems],
+                       "vectors_per_snr": V, "alpha": alpha, "kbest_K": 5, "snr_db": snrs},
+            "coherent": out, "jed": jed,
+            "cpu_baseline": {"value": 64 / cpu_s, "unit": "vectors/s", "cores": 1, "kind": "oracle",
+                             "sample": "exact SDR (float64 interior point) on 64 vectors of 64x16 QPSK at 10 dB"}}
+
+
 def run_counters(args):
     """One launch per product precision of a secondary workload, nothing
     else: the launches a rocprofv3 --pmc counter pass reads."""
@@ -454,6 +620,8 @@ def run_workload(args):
         return run_unfolded_workload(args)
     if args.workload == "fixed128x16":
         return run_fixed_workload(args)
+    if args.workload == "detectors":
+        return run_detectors_workload(args)
     if args.workload == "jed16x16":
         kind, B, U, mod, V, t_max, alpha = "jed", 16, 16, 2, 262144, 20, alpha_star("jed16x16")
         snrs, snr_timed, sample = [0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0], 6.0, 16384
