@@ -212,13 +212,22 @@ __device__ __forceinline__ float top_eigenvalue(const float* al, const float* b2
   return 0.5f * (lo + hi);
 }
 
+// The padded T is symmetric: its lower triangle is kept packed by rows
+// (half the LDS of the square, which doubles the waves a CU holds for the
+// four-tile kernels).
 template <int NT>
 struct VecLds {
   static constexpr int N1 = 16 * NT;
-  static constexpr int TT = (N1 + 1) * (N1 + 1);                 // padded T
+  static constexpr int TT = (N1 + 1) * (N1 + 2) / 2;             // packed padded T
   static constexpr int REGION = TT;
   static constexpr int FLOATS = REGION + (N1 + 1) + N1;          // + D + shuffle buffer
 };
+
+// Entry (i, j) of the packed symmetric T, either order.
+__device__ __forceinline__ int tix(int i, int j) {
+  const int hi = i > j ? i : j, lo = i > j ? j : i;
+  return hi * (hi + 1) / 2 + lo;
+}
 
 // One vector's problem: where its inputs and outputs are and its sizes.
 struct VecJob {
@@ -276,7 +285,10 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
   float bre[UTM], bim[UTM], ysq = 0.f;
 #pragma unroll
   for (int t = 0; t < UTM; ++t) { bre[t] = 0.f; bim[t] = 0.f; }
-  constexpr int kQ = 4;                        // row-quads per batch (double-buffered)
+  // row-quads per batch (double-buffered): the four-tile kernels have
+  // registers to spare in this phase (their peak is the loop's L~ tiles), and
+  // a deeper prefetch covers more of the load latency of a 64 KB channel
+  constexpr int kQ = NT == 4 ? 8 : 4;
   float2 hc[kQ][UTM], yc[kQ], hn[kQ][UTM], yn[kQ];
   auto load_batch = [&](int q0, float2 (&hb)[kQ][UTM], float2 (&yb)[kQ]) {
 #pragma unroll
@@ -345,23 +357,22 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
   for (int t = 0; t < UTM; ++t) { bre[t] = sum_quads(bre[t]); bim[t] = sum_quads(bim[t]); }
   ysq = sum_quads(ysq);                        // rows 4 q + g summed over the four g lanes
 
-  // T in padded indexing (eq. (2) coherent, eq. (5) joint detection)
+  // T in padded indexing (eq. (2) coherent, eq. (5) joint detection),
+  // lower triangle packed: the lane of entry (p, q) with p >= q writes it
+  // (on the diagonal tiles the lane of (q, p) holds the same sums)
   for (int e = lane; e < S::TT; e += 64) T[e] = 0.f;
   __syncthreads();
-  constexpr int LD = N1 + 1;
   auto put_tile = [&](const f4& re4, const f4& im4, int t1, int t2) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int p = 16 * t1 + 4 * g + r, q = 16 * t2 + n;
-      if (p >= U || q >= U) continue;
+      if (p >= U || q >= U || p < q) continue;
       const float gr = sg * re4[r], gi = p == q ? 0.f : sg * im4[r];
+      T[tix(p, q)] = gr;
       if (qpsk) {
-        T[p * LD + q] = gr; T[q * LD + p] = gr;
-        T[(U + p) * LD + U + q] = gr; T[(U + q) * LD + U + p] = gr;
-        T[p * LD + U + q] = -gi; T[(U + q) * LD + p] = -gi;
-        T[q * LD + U + p] = gi; T[(U + p) * LD + q] = gi;
-      } else {
-        T[p * LD + q] = gr; T[q * LD + p] = gr;
+        T[tix(U + p, U + q)] = gr;
+        T[tix(U + q, p)] = -gi;                  // T(p, U + q) = -Im G(p, q)
+        T[tix(U + p, q)] = gi;
       }
     }
   };
@@ -376,12 +387,12 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
       const int p = 16 * t + n;
       if (p < U) {
         // last column: -Hbar^T ybar in both modes
-        T[p * LD + N1] = -bre[t]; T[N1 * LD + p] = -bre[t];
-        if (qpsk) { T[(U + p) * LD + N1] = -bim[t]; T[N1 * LD + U + p] = -bim[t]; }
+        T[tix(N1, p)] = -bre[t];
+        if (qpsk) T[tix(N1, U + p)] = -bim[t];
       }
     }
   }
-  if (lane == 0) T[N1 * LD + N1] = sg * ysq;
+  if (lane == 0) T[tix(N1, N1)] = sg * ysq;
   __syncthreads();
 }
 
@@ -389,7 +400,7 @@ template <int NT, int P>
 __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, float* lds) {
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
-  float* T = lds;                        // [(N1+1)^2], padded index: real i < N-1 -> i, N-1 -> N1
+  float* T = lds;                        // packed, padded index: real i < N-1 -> i, N-1 -> N1
   float* Dl = lds + S::REGION;           // [N1+1]
   float* sh = Dl + (N1 + 1);             // [N1] layout shuffle
 
@@ -403,7 +414,6 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   const float sg = jed ? -1.f : 1.f;
 
   vec_build_T<NT, P>(job, jed, T);
-  constexpr int LD = N1 + 1;
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
   int bad = 0, deg = 0;
@@ -412,7 +422,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   const bool nonfinite = or_all(bad);
   for (int k = lane; k <= N1; k += 64) {
     const bool real_k = k < Nm1 || k == N1;
-    const float d = nonfinite ? 0.f : fabsf(T[k * LD + k]);
+    const float d = nonfinite ? 0.f : fabsf(T[tix(k, k)]);
     if (real_k && d == 0.f) deg = 1;
     Dl[k] = (d == 0.f || !real_k) ? 1.f : hsqrt(d);
   }
@@ -421,7 +431,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   __syncthreads();
   const float DN = Dl[N1];
   const float iDN = rcp(DN);
-  const float tNN = skip ? 0.f : T[N1 * LD + N1] * (iDN * iDN);
+  const float tNN = skip ? 0.f : T[tix(N1, N1)] * (iDN * iDN);
   float A[NT][NT][4];
   {
     const int jr = 4 * (n & 3) + (n >> 2);
@@ -434,7 +444,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int k = 16 * KT + 4 * s + g;
-          A[JT][KT][s] = skip ? 0.f : T[j * LD + k] * (idj * rcp(Dl[k]));
+          A[JT][KT][s] = skip ? 0.f : T[tix(j, k)] * (idj * rcp(Dl[k]));
         }
       });
     });
@@ -448,7 +458,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       const int j = 16 * JT + 4 * r + g;
       act[JT][r] = j < Nm1;
       Dc[JT][r] = Dl[j];
-      ct[JT][r] = skip ? 0.f : T[j * LD + N1] * (rcp(Dl[j]) * iDN);
+      ct[JT][r] = skip ? 0.f : T[tix(N1, j)] * (rcp(Dl[j]) * iDN);
     }
   });
   __syncthreads();   // T is dead from here on; sh may be reused freely
@@ -875,11 +885,13 @@ void fused_vec(FusedArgs a) {
 template <int NT>
 __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   constexpr int N1 = 16 * NT;
-  constexpr int LD = N1 + 1;
   constexpr int NMAX = N1 + 1;
-  __shared__ __align__(16) float T[VecLds<NT>::TT];
+  constexpr int kQ = spectral::kLanczosMax * NMAX;
+  // the packed T is dead once T~ is in Tr, and the Lanczos basis reuses it
+  __shared__ __align__(16) float TQ[VecLds<NT>::TT > kQ ? VecLds<NT>::TT : kQ];
+  float* T = TQ;
+  float* Q = TQ;
   __shared__ float Tr[NMAX * NMAX];
-  __shared__ float Q[spectral::kLanczosMax * NMAX];
   __shared__ float Dl[N1 + 1];
   __shared__ float al[spectral::kLanczosMax], be2[spectral::kLanczosMax];
   const int lane = threadIdx.x;
@@ -906,7 +918,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   const bool nonfinite = or_all(bad);
   for (int k = lane; k <= N1; k += 64) {
     const bool real_k = k < Nm1 || k == N1;
-    const float d = nonfinite ? 0.f : fabsf(T[k * LD + k]);
+    const float d = nonfinite ? 0.f : fabsf(T[tix(k, k)]);
     if (real_k && d == 0.f) deg = 1;
     Dl[k] = (d == 0.f || !real_k) ? 1.f : hsqrt(d);
   }
@@ -916,7 +928,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   for (int e = lane; e < N * N; e += 64) {
     const int i = e / N, j = e - i * N;
     const int pi = i < Nm1 ? i : N1, pj = j < Nm1 ? j : N1;
-    const float t = nonfinite ? 0.f : T[pi * LD + pj] * rcp(Dl[pi] * Dl[pj]);
+    const float t = nonfinite ? 0.f : T[tix(pi, pj)] * rcp(Dl[pi] * Dl[pj]);
     Tr[e] = t;
     Ttg[e] = t;
   }
@@ -1029,10 +1041,16 @@ __global__ void mixed_clear(int32_t* count) {
   if (threadIdx.x < kMixedBuckets) count[threadIdx.x] = 0;
 }
 
+constexpr int kAssignThreads = 1024;
+
 // Appends every vector to its bucket's list (order within a bucket is
 // arbitrary; each vector's result does not depend on it).  Vectors no fused
 // kernel covers get status TASER_VEC_UNSUPPORTED and decisions +1.
-__global__ void mixed_assign(FusedArgs a, MixedArgs m) {
+__global__ __launch_bounds__(kAssignThreads) void mixed_assign(FusedArgs a, MixedArgs m) {
+  __shared__ int blk_count[kMixedBuckets];
+  __shared__ int blk_base[kMixedBuckets];
+  if (threadIdx.x < kMixedBuckets) blk_count[threadIdx.x] = 0;
+  __syncthreads();
   const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   int b = -2;                                   // -2: past the end, -1: unsupported size
   if (v < a.V) {
@@ -1046,22 +1064,28 @@ __global__ void mixed_assign(FusedArgs a, MixedArgs m) {
       }
     }
   }
-  // One atomic per wave and bucket: the lanes of a bucket take consecutive
-  // slots after the wave's base (a per-lane atomic on three counters
-  // serialises 10^5 updates).
+  // Slots are handed out at three levels, so that the three global counters
+  // see one atomic per workgroup and bucket (atomics on one address
+  // serialise in L2: one per wave and bucket took 60 us for 10^5 vectors):
+  // lanes of a bucket take consecutive slots after their wave's offset,
+  // waves after their workgroup's offset (LDS atomics), workgroups after the
+  // bucket's global count.
   const int lane = threadIdx.x & 63;
+  int slot = 0;
   for (int bk = 0; bk < kMixedBuckets; ++bk) {
     const unsigned long long mask = __ballot(b == bk);
     if (mask == 0ull) continue;
     const int leader = __ffsll((unsigned long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&m.count[bk], (int)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (b == bk) {
-      const int rank = (int)__popcll(mask & ((1ull << lane) - 1ull));
-      m.list[(long long)bk * a.V + base + rank] = (int32_t)v;
-    }
+    int off = 0;
+    if (lane == leader) off = atomicAdd(&blk_count[bk], (int)__popcll(mask));
+    off = __shfl(off, leader, 64);
+    if (b == bk) slot = off + (int)__popcll(mask & ((1ull << lane) - 1ull));
   }
+  __syncthreads();
+  if (threadIdx.x < kMixedBuckets)
+    blk_base[threadIdx.x] = blk_count[threadIdx.x] ? atomicAdd(&m.count[threadIdx.x], blk_count[threadIdx.x]) : 0;
+  __syncthreads();
+  if (b >= 0) m.list[(long long)b * a.V + blk_base[b] + slot] = (int32_t)v;
 }
 
 template <int NT, int W>
@@ -1119,7 +1143,8 @@ size_t mixed_workspace_bytes(int V) {
 hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const taser_mixed_launch_t* launch,
                         hipStream_t s) {
   hipLaunchKernelGGL(mixed_clear, dim3(1), dim3(64), 0, s, m.count);
-  hipLaunchKernelGGL(mixed_assign, dim3((a.V + 255) / 256), dim3(256), 0, s, a, m);
+  hipLaunchKernelGGL(mixed_assign, dim3((a.V + kAssignThreads - 1) / kAssignThreads), dim3(kAssignThreads), 0,
+                     s, a, m);
   if (launch && launch->single_launch) {
     const dim3 grid(a.V), block(64);
     if (a.prec == TASER_PREC_BF16)
