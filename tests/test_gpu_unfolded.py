@@ -136,6 +136,30 @@ def test_fp32_gradient_close_to_fp64(gpu_lib, unf):
     assert np.max(np.abs(g - g_ref)) <= 1e-3 * np.max(np.abs(g_ref)), (g, g_ref)
 
 
+@pytest.mark.parametrize("dtype_name", ["float32", "float64"])
+def test_empty_batch_backward_gives_zero_gradient(gpu_lib, dtype_name):
+    """dLoss/dalpha is a sum over the batch, so an empty batch has gradient
+    zero: the backward of V = 0 writes zeros into its uninitialised output
+    (a NaN-filled block of the same size is freed just before, so the
+    caching allocator hands that memory back)."""
+    import torch
+    dt = getattr(torch, dtype_name)
+    N, t_max = 33, 6
+    Tt = torch.empty((0, N, N), dtype=dt, device="cuda")
+    D = torch.empty((0, N), dtype=dt, device="cuda")
+    lam = torch.empty((0,), dtype=dt, device="cuda")
+    alpha = torch.full((t_max,), 0.5, dtype=dt, device="cuda")
+    L, ckpt, u = gpu_lib.unfolded_forward(Tt, D, lam, alpha)
+    assert L.shape == (0, N * (N + 1) // 2)
+    dL = torch.empty((0, N * (N + 1) // 2), dtype=dt, device="cuda")
+    junk = torch.full((t_max,), float("nan"), dtype=dt, device="cuda")
+    del junk
+    torch.cuda.synchronize()
+    g = gpu_lib.unfolded_backward(u, Tt, D, lam, alpha, ckpt, dL)
+    torch.cuda.synchronize()
+    assert torch.equal(g, torch.zeros_like(g))
+
+
 def test_training_lowers_loss(gpu_lib, unf):
     """A few Adam steps on the step sizes (FP32 kernels) lower the training
     loss on fresh batches, and the schedule stays finite."""
