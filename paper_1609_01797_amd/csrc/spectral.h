@@ -12,7 +12,6 @@ namespace spectral {
 // overloaded systems (U > B), whose leading eigenvalues crowd together.
 constexpr int kLanczosMax = 24;
 constexpr int kLanczosWellPosed = 16;
-constexpr int kReorthBlock = 8;    // basis vectors per batch of reductions
 
 // Sum over the 64 lanes of a wave, on the vector ALUs: rotations inside each
 // 16-lane row (DPP row_ror 8, 4, 2, 1), then the gfx950 lane swaps across
@@ -88,7 +87,7 @@ __device__ inline float start_entry(int i) {
 
 // ||T~||_2 (largest |eigenvalue|) of the symmetric N x N matrix T, row-major
 // in LDS, by Lanczos with two passes of classical Gram-Schmidt against every
-// basis vector (CGS2) and a multisection of the Ritz tridiagonal.  Run by all 64
+// basis vector and a multisection of the Ritz tridiagonal.  Run by all 64
 // lanes of one wave (N <= 3 * 64); Q: LDS scratch of kLanczosMax * N floats,
 // al / be2: LDS arrays of kLanczosMax floats.  Every lane returns the value.
 __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, float* Q, float* al,
@@ -151,39 +150,15 @@ __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, flo
     m = j + 1;
     scale = fmaxf(scale, fabsf(alpha_j));
     if (j == m_cap - 1) break;
-    // two passes of classical Gram-Schmidt against every Lanczos vector:
-    // the coefficients of a pass all come from the same w, eight basis
-    // vectors at a time, so their eight wave reductions are independent and
-    // overlap instead of waiting on one another
+    // two passes of classical Gram-Schmidt against every Lanczos vector
     for (int pass = 0; pass < 2; ++pass) {
-      float wn[3] = {w[0], w[1], w[2]};
-      for (int i0 = 0; i0 <= j; i0 += kReorthBlock) {
-        float c[kReorthBlock];
-#pragma unroll
-        for (int b = 0; b < kReorthBlock; ++b) {
-          const int i = i0 + b;
-          float p = 0.f;
-#pragma unroll
-          for (int s = 0; s < 3; ++s) {
-            const int r = lane + s * kWave;
-            if (i <= j && r < N) p += w[s] * Q[(size_t)i * N + r];
-          }
-          c[b] = p;
-        }
-#pragma unroll
-        for (int b = 0; b < kReorthBlock; ++b) c[b] = wave_sum(c[b]);
-#pragma unroll
-        for (int b = 0; b < kReorthBlock; ++b) {
-          const int i = i0 + b;
-#pragma unroll
-          for (int s = 0; s < 3; ++s) {
-            const int r = lane + s * kWave;
-            if (i <= j && r < N) wn[s] -= c[b] * Q[(size_t)i * N + r];
-          }
-        }
+      for (int i = 0; i <= j; ++i) {
+        const float* qi = Q + (size_t)i * N;
+        float c = 0.f;
+        for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) c += w[s] * qi[r]; }
+        c = wave_sum(c);
+        for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) w[s] -= c * qi[r]; }
       }
-#pragma unroll
-      for (int s = 0; s < 3; ++s) w[s] = wn[s];
     }
     float bb = 0.f;
     for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) bb += w[s] * w[s]; }
