@@ -131,6 +131,39 @@ def test_kbest(gpu_lib, B, U, mod, snr, K):
     np.testing.assert_allclose(res, mine, rtol=1e-4, atol=1e-4 * np.abs(mine).max())
 
 
+@pytest.mark.parametrize("B, U, mod", [(8, 4, oracle.BPSK), (6, 2, oracle.QPSK), (4, 1, oracle.BPSK)])
+def test_kbest_keeping_every_path_is_ml(gpu_lib, B, U, mod):
+    """With K >= 2^M no path is ever dropped, so K-best is exhaustive ML:
+    M = 4, 4 and 1 real dimensions with K = 16 give the GPU's exhaustive-ML
+    decisions wherever the FP64 runner-up is more than 1e-5 behind."""
+    V = 128
+    d = sim.gen_mimo(B, U, mod, V, 1, 0.0, sim.seed_for(1, snr_index=124, shard=B + U))
+    sb_k, res_k = _run(gpu_lib, gpu_lib.REF_KBEST, d, B, U, mod, K=16)
+    sb_m, res_m = _run(gpu_lib, gpu_lib.REF_ML, d, B, U, mod)
+    costs, S = _all_costs(d["H"], d["y"], mod)
+    order = np.sort(costs, axis=1)
+    clear = order[:, 1] > order[:, 0] * (1 + 1e-5)
+    S_ml = S[np.argmin(costs, axis=1)].astype(np.int8)
+    np.testing.assert_array_equal(sb_k[clear], S_ml[clear])
+    np.testing.assert_array_equal(sb_m[clear], S_ml[clear])
+    np.testing.assert_allclose(res_k, res_m, rtol=1e-4, atol=1e-4 * np.abs(res_m).max())
+
+
+@pytest.mark.parametrize("kind", ["mf", "mmse", "kbest"])
+def test_shared_channel_matches_repeated_channel(gpu_lib, kind):
+    """y_per_H = 8 (eight received vectors per channel matrix) gives the same
+    outputs, bit for bit, as the same channel repeated per vector."""
+    import torch
+    B, U, mod, yph = 32, 8, oracle.QPSK, 8
+    d = sim.gen_mimo(B, U, mod, 40, yph, 3.0, sim.seed_for(1, snr_index=125))
+    k = {"mf": gpu_lib.REF_MF, "mmse": gpu_lib.REF_MMSE, "kbest": gpu_lib.REF_KBEST}[kind]
+    sb1, soft1 = _run(gpu_lib, k, d, B, U, mod, K=5, n0=d["N0"], yph=yph)
+    rep = dict(d, H=np.ascontiguousarray(np.repeat(d["H"], yph, axis=0)))
+    sb2, soft2 = _run(gpu_lib, k, rep, B, U, mod, K=5, n0=d["N0"], yph=1)
+    np.testing.assert_array_equal(sb1, sb2)
+    np.testing.assert_array_equal(soft1, soft2)
+
+
 def test_reference_rejects_and_empty(gpu_lib):
     import ctypes
     lib = gpu_lib.load()
