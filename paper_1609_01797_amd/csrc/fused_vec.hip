@@ -109,7 +109,10 @@ __device__ __forceinline__ float sum_rows16(float x) {
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+  // every lane of a row has a valid source for the controls used here, so
+  // bound_ctrl (0 for an invalid source) never applies; it spares the
+  // compiler a zero-initialised destination register per move
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
 // One level of a transpose-reduction inside 16-lane rows: each lane swaps
