@@ -249,7 +249,7 @@ struct VecJob {
 // [(16 NT + 1)^2] in padded indexing (real index i < N - 1 -> i, N - 1 ->
 // 16 NT; the padding rows and columns are zero).  One wave; ends with a
 // barrier.
-template <int NT, int P>
+template <int NT, int P, bool GAUSS>
 __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* T) {
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
@@ -282,9 +282,18 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
     if (!jed) return y0;
     return make_float2(y0.x * s0.x - y0.y * s0.y, y0.x * s0.y + y0.y * s0.x);
   };
-  f4 gre[3], gim[3];                           // tiles (0,0), (1,0), (1,1)
+  // tiles (0,0), (1,0), (1,1).  QPSK with GAUSS: Gauss's three real products
+  // per complex tile; for conj(a + jb) (c + jd), k1 = (a - b) c,
+  // k2 = a (d - c), k3 = b (c + d), so Re = k1 + k3 and Im = ad - bc = k1 + k2
+  // (gre holds k1, gim k2, gk3 k3).  It saves a quarter of the Gram MFMAs but
+  // needs a third set of accumulators: the four-tile kernels use it (every
+  // variant of a size takes the same arithmetic, so launch choices do not
+  // change results); with one or two tiles the spills of the five-wave
+  // budget cost more than the products saved, and the four products of Re
+  // and Im are taken directly.  BPSK needs only Re G (two products into gre).
+  f4 gre[3], gim[3], gk3[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) { gre[k] = f4{0.f, 0.f, 0.f, 0.f}; gim[k] = gre[k]; }
+  for (int k = 0; k < 3; ++k) { gre[k] = f4{0.f, 0.f, 0.f, 0.f}; gim[k] = gre[k]; gk3[k] = gre[k]; }
   float bre[UTM], bim[UTM], ysq = 0.f;
 #pragma unroll
   for (int t = 0; t < UTM; ++t) { bre[t] = 0.f; bim[t] = 0.f; }
@@ -317,24 +326,45 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
         // pipe (here and in the tril products below); with 16-bit products it
         // made mixed batches slower
         if constexpr (P == TASER_PREC_F32) __builtin_amdgcn_s_setprio(1);
-        gre[0] = mfma(h0.x, h0.x, gre[0]);       // Re G = Hr^T Hr + Hi^T Hi
-        gre[0] = mfma(h0.y, h0.y, gre[0]);
-        if constexpr (Q) {
-          gim[0] = mfma(h0.x, h0.y, gim[0]);     // Im G = Hr^T Hi - Hi^T Hr
-          gim[0] = mfma(h0.y, -h0.x, gim[0]);
-        }
-        if constexpr (UTM == 2) {
-          if (UT == 2) {
-            const float2 h1 = hc[q][1];
-            gre[1] = mfma(h1.x, h0.x, gre[1]);
-            gre[1] = mfma(h1.y, h0.y, gre[1]);
-            gre[2] = mfma(h1.x, h1.x, gre[2]);
-            gre[2] = mfma(h1.y, h1.y, gre[2]);
-            if constexpr (Q) {
-              gim[1] = mfma(h1.x, h0.y, gim[1]);
-              gim[1] = mfma(h1.y, -h0.x, gim[1]);
-              gim[2] = mfma(h1.x, h1.y, gim[2]);
-              gim[2] = mfma(h1.y, -h1.x, gim[2]);
+        if constexpr (Q && GAUSS) {
+          // A side (a - b), a, b of the left tile; B side c, (d - c), (c + d)
+          // of the right tile
+          const float amb0 = h0.x - h0.y, dmc0 = h0.y - h0.x, cpd0 = h0.x + h0.y;
+          gre[0] = mfma(amb0, h0.x, gre[0]);
+          gim[0] = mfma(h0.x, dmc0, gim[0]);
+          gk3[0] = mfma(h0.y, cpd0, gk3[0]);
+          if constexpr (UTM == 2) {
+            if (UT == 2) {
+              const float2 h1 = hc[q][1];
+              const float amb1 = h1.x - h1.y, dmc1 = h1.y - h1.x, cpd1 = h1.x + h1.y;
+              gre[1] = mfma(amb1, h0.x, gre[1]);
+              gim[1] = mfma(h1.x, dmc0, gim[1]);
+              gk3[1] = mfma(h1.y, cpd0, gk3[1]);
+              gre[2] = mfma(amb1, h1.x, gre[2]);
+              gim[2] = mfma(h1.x, dmc1, gim[2]);
+              gk3[2] = mfma(h1.y, cpd1, gk3[2]);
+            }
+          }
+        } else {
+          gre[0] = mfma(h0.x, h0.x, gre[0]);     // Re G = Hr^T Hr + Hi^T Hi
+          gre[0] = mfma(h0.y, h0.y, gre[0]);
+          if constexpr (Q) {
+            gim[0] = mfma(h0.x, h0.y, gim[0]);   // Im G = Hr^T Hi - Hi^T Hr
+            gim[0] = mfma(h0.y, -h0.x, gim[0]);
+          }
+          if constexpr (UTM == 2) {
+            if (UT == 2) {
+              const float2 h1 = hc[q][1];
+              gre[1] = mfma(h1.x, h0.x, gre[1]);
+              gre[1] = mfma(h1.y, h0.y, gre[1]);
+              gre[2] = mfma(h1.x, h1.x, gre[2]);
+              gre[2] = mfma(h1.y, h1.y, gre[2]);
+              if constexpr (Q) {
+                gim[1] = mfma(h1.x, h0.y, gim[1]);
+                gim[1] = mfma(h1.y, -h0.x, gim[1]);
+                gim[2] = mfma(h1.x, h1.y, gim[2]);
+                gim[2] = mfma(h1.y, -h1.x, gim[2]);
+              }
             }
           }
         }
@@ -354,8 +384,19 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
       }
     }
   };
-  if (qpsk) rows(std::true_type{});
-  else rows(std::false_type{});
+  if (qpsk) {
+    rows(std::true_type{});
+    if constexpr (GAUSS) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const f4 k1 = gre[k];
+        gre[k] = k1 + gk3[k];
+        gim[k] = k1 + gim[k];
+      }
+    }
+  } else {
+    rows(std::false_type{});
+  }
 #pragma unroll
   for (int t = 0; t < UTM; ++t) { bre[t] = sum_quads(bre[t]); bim[t] = sum_quads(bim[t]); }
   ysq = sum_quads(ysq);                        // rows 4 q + g summed over the four g lanes
@@ -399,7 +440,7 @@ __device__ __forceinline__ void vec_build_T(const VecJob& job, bool jed, float* 
   __syncthreads();
 }
 
-template <int NT, int P>
+template <int NT, int P, bool GAUSS = (NT == 4)>
 __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, float* lds) {
   constexpr int N1 = 16 * NT;
   using S = VecLds<NT>;
@@ -416,7 +457,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
   const bool qpsk = job.mod == TASER_QPSK;
   const float sg = jed ? -1.f : 1.f;
 
-  vec_build_T<NT, P>(job, jed, T);
+  vec_build_T<NT, P, GAUSS>(job, jed, T);
 
   // ---------------- Jacobi preconditioning (Section III-C) ----------------
   int bad = 0, deg = 0;
@@ -913,7 +954,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
     job.y = a.y + v * (long long)a.B;
     job.s0 = make_float2(1.f, 0.f);
   }
-  vec_build_T<NT, TASER_PREC_F32>(job, jed, T);
+  vec_build_T<NT, TASER_PREC_F32, NT == 4>(job, jed, T);
 
   int bad = 0, deg = 0;
   for (int e = lane; e < VecLds<NT>::TT; e += 64)
