@@ -86,8 +86,9 @@ __device__ inline float start_entry(int i) {
 }
 
 // ||T~||_2 (largest |eigenvalue|) of the symmetric N x N matrix T, row-major
-// in LDS, by Lanczos with two passes of classical Gram-Schmidt against every
-// basis vector and a multisection of the Ritz tridiagonal.  Run by all 64
+// in LDS, by Lanczos with full reorthogonalisation (two passes of modified
+// Gram-Schmidt against every basis vector: each coefficient is removed
+// before the next is taken) and a multisection of the Ritz tridiagonal.  Run by all 64
 // lanes of one wave (N <= 3 * 64); Q: LDS scratch of kLanczosMax * N floats,
 // al / be2: LDS arrays of kLanczosMax floats.  Every lane returns the value.
 __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, float* Q, float* al,
@@ -150,7 +151,7 @@ __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, flo
     m = j + 1;
     scale = fmaxf(scale, fabsf(alpha_j));
     if (j == m_cap - 1) break;
-    // two passes of classical Gram-Schmidt against every Lanczos vector
+    // two passes of modified Gram-Schmidt against every Lanczos vector
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i <= j; ++i) {
         const float* qi = Q + (size_t)i * N;
