@@ -132,9 +132,11 @@ def run_mixed_workload(args):
         def call(cfg=None):
             cfg = cfg or autotune.DEFAULT
             return taser.run_mixed(desc, *ins, blocks=cfg["blocks"], waves=cfg["waves"],
-                                   single=bool(cfg["single"]), out=out, ws=ws)
+                                   single=bool(cfg["single"]), concurrent=bool(cfg.get("concurrent", 0)),
+                                   out=out, ws=ws)
         ms_default = _time(lambda: call(None), args.steps, args.warmup, stream)
         ms_single = _time(lambda: call(dict(autotune.DEFAULT, single=1)), args.steps, args.warmup, stream)
+        ms_concurrent = _time(lambda: call(dict(autotune.DEFAULT, concurrent=1)), args.steps, args.warmup, stream)
         best, tune_report, trace = autotune.tune_mixed(desc, ins, reps=3)
         ms_tuned = _time(lambda: call(best), args.steps, args.warmup, stream)
         # graph replay of the tuned call
@@ -150,7 +152,8 @@ def run_mixed_workload(args):
         for c, (idx, rsb) in samp.items():
             fl += int(np.count_nonzero(sb[idx, :rsb.shape[1]] != rsb))
         flips[name] = fl
-        paths[name] = {"ms_default": ms_default, "ms_single_launch": ms_single, "ms_tuned": ms_tuned,
+        paths[name] = {"ms_default": ms_default, "ms_single_launch": ms_single,
+                       "ms_concurrent_buckets": ms_concurrent, "ms_tuned": ms_tuned,
                        "ms_graph": ms_graph, "tuned": best, "autotune": tune_report,
                        "vectors_per_s": V / (min(ms_tuned, ms_graph) * 1e-3),
                        "ber": err / int(mask.sum())}

@@ -371,11 +371,23 @@ int32_t taser_calibrate_elements(void);
                 SIMD for N-1 <= 16, 4 for <= 32, 3 for <= 64);
      single_launch  1: every bucket in one launch over one work queue (the
                 bucket lists, largest problems first), with the registers of
-                the largest size; blocks and waves are then ignored. */
+                the largest size; blocks, waves and concurrent are then
+                ignored;
+     concurrent 1: the bucket kernels go to three streams, the caller's and
+                two side streams of the library (created on the first such
+                call on a device, default priority, kept until the process
+                ends), forked from and joined back into the caller's stream
+                with events, so that they can share the GPU; the call is
+                still ordered on the caller's stream and capturable, but the
+                first concurrent call on a device must not be made while a
+                stream is being captured (it creates the side streams).
+                Calls from several host threads are serialised while they
+                enqueue. */
 typedef struct {
   int32_t blocks[3];
   int32_t waves[3];
   int32_t single_launch;
+  int32_t concurrent;
 } taser_mixed_launch_t;
 
 taser_status_t taser_mixed_workspace_size(const taser_desc_t* desc, size_t* bytes);

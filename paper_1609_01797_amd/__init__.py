@@ -51,8 +51,10 @@ class MixedLaunch(ctypes.Structure):
     """Launch choices of a mixed batch (taser_mixed_launch_t): grid per size
     bucket (N-1 <= 16, <= 32, <= 64; 0 = one workgroup per vector, n > 0 = a
     persistent grid of n workgroups), register budget per bucket (0 default,
-    1 alternative) and single_launch (every bucket in one launch)."""
-    _fields_ = [("blocks", ctypes.c_int32 * 3), ("waves", ctypes.c_int32 * 3), ("single_launch", ctypes.c_int32)]
+    1 alternative), single_launch (every bucket in one launch) and
+    concurrent (the bucket kernels on three streams)."""
+    _fields_ = [("blocks", ctypes.c_int32 * 3), ("waves", ctypes.c_int32 * 3), ("single_launch", ctypes.c_int32),
+                ("concurrent", ctypes.c_int32)]
 
 
 class UnfoldedDesc(ctypes.Structure):
@@ -493,13 +495,14 @@ MIXED_STRIDE = 64
 
 
 def run_mixed(desc: Desc, Bv, Uv, modv, H_off, y_off, H, y, tau=None, want_margin=False,
-              blocks=None, out=None, ws=None, waves=None, single=False):
+              blocks=None, out=None, ws=None, waves=None, single=False, concurrent=False):
     """Mixed-size coherent batch in one call (``taser_run_mixed``).
     Bv, Uv, modv: int32 [V]; H_off, y_off: int64 [V] (complex elements);
     H, y: flat complex64 device tensors.  Launch choices (e.g. from the
     autotuner): ``blocks`` grid per bucket (3 ints, 0 = default), ``waves``
     register budget per bucket (3 ints, 0 default, 1 alternative),
-    ``single`` every bucket in one launch.  Returns dict with sbar int8
+    ``single`` every bucket in one launch, ``concurrent`` the bucket kernels
+    on three streams.  Returns dict with sbar int8
     [V, 64] (first N_v - 1 entries valid), status (+ margin)."""
     torch = _torch()
     lib = load()
@@ -532,6 +535,7 @@ def run_mixed(desc: Desc, Bv, Uv, modv, H_off, y_off, H, y, tau=None, want_margi
         for i, w in enumerate(waves):
             launch.waves[i] = int(w)
     launch.single_launch = 1 if single else 0
+    launch.concurrent = 1 if concurrent else 0
     st = lib.taser_run_mixed(ctypes.byref(desc), *(ctypes.c_void_p(t.data_ptr()) for t in (Bv, Uv, modv, H_off, y_off, H, y)),
                              pt, ctypes.c_void_p(res["sbar"].data_ptr()),
                              ctypes.c_void_p(res["margin"].data_ptr()) if want_margin else None,

@@ -6,7 +6,8 @@ n > 0 = a persistent grid of n workgroups walking the bucket's vector list)
 and the register budget of the one-workgroup-per-vector kernel (0 = the
 default build, 1 = the alternative: more waves per SIMD for one and four
 column tiles, fewer for two); and, for the whole batch, a single launch of
-one kernel over one work queue with the registers of the largest size.
+one kernel over one work queue with the registers of the largest size, or
+the bucket kernels on three streams at once (``concurrent``).
 ``tune_mixed`` searches them on the device by coordinate descent (one
 choice at a time, the others at their current best, short timings), then
 times the proposal and the default interleaved and adopts the proposal only
@@ -57,7 +58,7 @@ def save_cache(cache, path=DEFAULT_CACHE):
         os.replace(tmp, path)
 
 
-DEFAULT = {"blocks": [0, 0, 0], "waves": [0, 0, 0], "single": 0}
+DEFAULT = {"blocks": [0, 0, 0], "waves": [0, 0, 0], "single": 0, "concurrent": 0}
 
 
 def cached_config(prec, t_max, num_vectors, path=DEFAULT_CACHE):
@@ -65,7 +66,8 @@ def cached_config(prec, t_max, num_vectors, path=DEFAULT_CACHE):
     rec = load_cache(path).get(cache_key(prec, t_max, num_vectors))
     if not rec:
         return dict(DEFAULT)
-    return {"blocks": list(rec["blocks"]), "waves": list(rec["waves"]), "single": int(rec["single"])}
+    return {"blocks": list(rec["blocks"]), "waves": list(rec["waves"]), "single": int(rec["single"]),
+            "concurrent": int(rec.get("concurrent", 0))}
 
 
 def _time_call(fn, reps=5):
@@ -101,7 +103,7 @@ def compare(fn_a, fn_b, rounds=15, reps=3):
 
 
 def _key(cfg):
-    return (tuple(cfg["blocks"]), tuple(cfg["waves"]), cfg["single"])
+    return (tuple(cfg["blocks"]), tuple(cfg["waves"]), cfg["single"], cfg.get("concurrent", 0))
 
 
 def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sweeps=1, rounds=15):
@@ -118,12 +120,14 @@ def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sw
 
     def call(cfg):
         return lambda: taser.run_mixed(desc, *args, blocks=cfg["blocks"], waves=cfg["waves"],
-                                       single=bool(cfg["single"]), out=out)
+                                       single=bool(cfg["single"]),
+                                       concurrent=bool(cfg.get("concurrent", 0)), out=out)
 
     def variant(cfg, field, b, value):
-        new = {"blocks": list(cfg["blocks"]), "waves": list(cfg["waves"]), "single": cfg["single"]}
-        if field == "single":
-            new["single"] = value
+        new = {"blocks": list(cfg["blocks"]), "waves": list(cfg["waves"]), "single": cfg["single"],
+               "concurrent": cfg.get("concurrent", 0)}
+        if field in ("single", "concurrent"):
+            new[field] = value
         else:
             new[field][b] = value
         return new
@@ -132,7 +136,7 @@ def tune_mixed(desc, args, candidates=CANDIDATES, path=DEFAULT_CACHE, reps=3, sw
     best_ms = _time_call(call(best), reps)
     seen = {_key(best): best_ms}
     trace = [{"config": best, "ms": best_ms}]
-    choices = [("single", 0, (0, 1))]
+    choices = [("single", 0, (0, 1)), ("concurrent", 0, (0, 1))]
     for b in range(3):
         choices += [("blocks", b, candidates), ("waves", b, (0, 1))]
     for _ in range(sweeps):

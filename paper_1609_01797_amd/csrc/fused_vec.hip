@@ -16,6 +16,7 @@
 // matrix-vector products through the same A registers on the vector ALUs.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "spectral.h"
@@ -1184,6 +1185,40 @@ size_t mixed_workspace_bytes(int V) {
   return 256 + (size_t)kMixedBuckets * (size_t)V * sizeof(int32_t);
 }
 
+namespace {
+// Two side streams and their fork / join events per device, created on first
+// use (default priority, non-blocking) and kept until the process ends.  The
+// mutex also covers the launch sequence that uses them, so calls from
+// several host threads do not re-record an event between its record and
+// the waits on it.
+constexpr int kForkDevices = 64;
+struct ForkJoin {
+  hipStream_t side[2];
+  hipEvent_t fork, join[2];
+  bool ready;
+};
+ForkJoin g_fork[kForkDevices];
+std::mutex g_fork_mu;
+
+hipError_t fork_join_for_device(ForkJoin** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kForkDevices) return hipErrorInvalidDevice;
+  ForkJoin& f = g_fork[dev];
+  if (!f.ready) {
+    for (int i = 0; i < 2; ++i) {
+      if ((e = hipStreamCreateWithFlags(&f.side[i], hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&f.join[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if ((e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    f.ready = true;
+  }
+  *out = &f;
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const taser_mixed_launch_t* launch,
                         hipStream_t s) {
   hipLaunchKernelGGL(mixed_clear, dim3(1), dim3(64), 0, s, m.count);
@@ -1199,14 +1234,36 @@ hipError_t launch_mixed(const FusedArgs& a, const MixedArgs& m, const taser_mixe
       hipLaunchKernelGGL(fused_vec_mixed_all<TASER_PREC_F32>, grid, block, 0, s, a, m);
     return hipGetLastError();
   }
-  for (int b = 0; b < kMixedBuckets; ++b) {
+  auto bucket = [&](int b, hipStream_t st) {
     const int g = launch ? launch->blocks[b] : 0;
     const int w = launch ? launch->waves[b] : 0;
-    if (b == 0) launch_mixed_nt<1>(a, m, b, g, w, s);
-    if (b == 1) launch_mixed_nt<2>(a, m, b, g, w, s);
-    if (b == 2) launch_mixed_nt<4>(a, m, b, g, w, s);
+    if (b == 0) launch_mixed_nt<1>(a, m, b, g, w, st);
+    if (b == 1) launch_mixed_nt<2>(a, m, b, g, w, st);
+    if (b == 2) launch_mixed_nt<4>(a, m, b, g, w, st);
+  };
+  if (!(launch && launch->concurrent)) {
+    for (int b = 0; b < kMixedBuckets; ++b) bucket(b, s);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  // the three bucket kernels on three streams, so that the GPU can place
+  // waves of one bucket beside those of another (the largest problems'
+  // register budget leaves room on each SIMD for the small ones)
+  std::lock_guard<std::mutex> lock(g_fork_mu);
+  ForkJoin* f = nullptr;
+  hipError_t e = fork_join_for_device(&f);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(f->fork, s)) != hipSuccess) return e;
+  for (int i = 0; i < 2; ++i)
+    if ((e = hipStreamWaitEvent(f->side[i], f->fork, 0)) != hipSuccess) return e;
+  bucket(2, s);
+  bucket(1, f->side[0]);
+  bucket(0, f->side[1]);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int i = 0; i < 2; ++i) {
+    if ((e = hipEventRecord(f->join[i], f->side[i])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, f->join[i], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int fused_vec_tiles(const FusedArgs& a) {

@@ -407,6 +407,7 @@ taser_status_t taser_run_mixed(const taser_desc_t* desc, const int32_t* Bv, cons
       if (launch->waves[b] != 0 && launch->waves[b] != 1) return TASER_ERR_ARG;
     }
     if (launch->single_launch != 0 && launch->single_launch != 1) return TASER_ERR_ARG;
+    if (launch->concurrent != 0 && launch->concurrent != 1) return TASER_ERR_ARG;
   }
   const size_t need = mixed_workspace_bytes(desc->num_vectors);
   if (!ws || ws_bytes < need) return TASER_ERR_WORKSPACE;

@@ -151,6 +151,9 @@ def test_mixed_entry_rejects_bad_arguments():
     launch.waves[2] = 1
     launch.single_launch = 3
     assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
+    launch.single_launch = 0
+    launch.concurrent = -1
+    assert lib.taser_run_mixed(ctypes.byref(d), *ok_args, z, one, z, 64, one, ctypes.byref(launch), one, 1 << 20, z) == taser.ERR_ARG
 
 
 def test_fused_entry_points_accept_an_empty_batch():

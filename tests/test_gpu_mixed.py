@@ -87,18 +87,28 @@ def test_mixed_launch_configs_agree(gpu_lib, mixed_case):
         torch.cuda.synchronize()
         for k in ("sbar", "margin", "status"):
             assert torch.equal(r[k], base[k]), (blocks, k)
-    # the alternative register budgets and the single launch over one work
-    # queue run the same arithmetic
-    for waves, single in (([1, 1, 1], False), ([1, 0, 1], False), ([0, 0, 0], True), ([1, 1, 1], True)):
-        r = gpu_lib.run_mixed(desc, *ins, want_margin=True, waves=waves, single=single)
+    # the alternative register budgets, the single launch over one work
+    # queue and the bucket kernels on three streams run the same arithmetic
+    for waves, single, conc in (([1, 1, 1], False, False), ([1, 0, 1], False, False),
+                                ([0, 0, 0], True, False), ([1, 1, 1], True, False),
+                                ([0, 0, 0], False, True), ([1, 0, 1], False, True)):
+        r = gpu_lib.run_mixed(desc, *ins, want_margin=True, waves=waves, single=single, concurrent=conc)
         torch.cuda.synchronize()
         for k in ("sbar", "margin", "status"):
-            assert torch.equal(r[k], base[k]), (waves, single, k)
+            assert torch.equal(r[k], base[k]), (waves, single, conc, k)
+    # a persistent grid on the side streams
+    r = gpu_lib.run_mixed(desc, *ins, want_margin=True, blocks=[7, 3, 2], concurrent=True)
+    torch.cuda.synchronize()
+    for k in ("sbar", "margin", "status"):
+        assert torch.equal(r[k], base[k]), ("blocks concurrent", k)
 
 
-def test_mixed_graph_capture_replay(gpu_lib, mixed_case):
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_mixed_graph_capture_replay(gpu_lib, mixed_case, concurrent):
     """The mixed call captured into a HIP graph gives the eager result on
-    every replay, with unrelated eager work and synchronisation in between."""
+    every replay, with unrelated eager work and synchronisation in between
+    (with concurrent buckets the capture forks into the library's side
+    streams and joins back)."""
     import torch
     d, _ = mixed_case
     V = len(d["cls"])
@@ -112,11 +122,13 @@ def test_mixed_graph_capture_replay(gpu_lib, mixed_case):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        gpu_lib.run_mixed(desc, *ins, want_margin=True, out=out, ws=ws)   # warm up on the side stream
+        # warm up on the side stream (this also creates the library's side
+        # streams, which cannot be created while a stream is being captured)
+        gpu_lib.run_mixed(desc, *ins, want_margin=True, out=out, ws=ws, concurrent=concurrent)
     torch.cuda.current_stream().wait_stream(s)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        gpu_lib.run_mixed(desc, *ins, want_margin=True, out=out, ws=ws)
+        gpu_lib.run_mixed(desc, *ins, want_margin=True, out=out, ws=ws, concurrent=concurrent)
     for rep in range(4):
         for k in out:
             out[k].zero_()
