@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define TASER_ABI_VERSION 2
+#define TASER_ABI_VERSION 3
 #define TASER_MAX_N 129          /* largest problem size N the library accepts */
 #define TASER_MAX_VECTORS (1 << 30) /* largest num_vectors any entry point accepts
                                        (kernel indices stay within 32 bits) */

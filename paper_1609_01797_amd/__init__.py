@@ -28,6 +28,7 @@ BPSK, QPSK = 1, 2
 COHERENT, JED = 0, 1
 PREC_F32, PREC_BF16, PREC_F16, PREC_FIXED14 = 0, 1, 2, 3
 TAU_SPECTRAL, TAU_GIVEN = 0, 1
+ABI_VERSION = 3           # TASER_ABI_VERSION of include/taser.h (struct layouts of this binding)
 FLAG_LITERAL_LAST = 1
 VEC_DEGENERATE, VEC_NONFINITE, VEC_ZERO_NORM, VEC_VNN_NONPOS, VEC_UNSUPPORTED = 1, 2, 4, 8, 16
 
@@ -79,6 +80,9 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     D = ctypes.POINTER(Desc)
     lib.taser_abi_version.restype = ctypes.c_int
+    if lib.taser_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.taser_abi_version()}, the binding expects "
+                          f"{ABI_VERSION}: rebuild it with `python -m paper_1609_01797_amd.build`")
     lib.taser_debug_inject_device_error.restype = ctypes.c_int
     lib.taser_debug_inject_device_error.argtypes = [ctypes.c_int32]
     lib.taser_status_string.restype = ctypes.c_char_p

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_sizes():
     lib = taser.load()
-    assert lib.taser_abi_version() == 2
+    assert lib.taser_abi_version() == 3
     assert lib.taser_problem_size(16, taser.QPSK) == 33
     assert lib.taser_problem_size(32, taser.BPSK) == 33
     assert lib.taser_problem_size(0, taser.QPSK) == -1
