@@ -192,3 +192,45 @@ def test_mixed_full_batch_bench_configuration(gpu_lib, prec):
         ref = oracle.detect_coherent(H, y, mod, alpha=alpha, t_max=10)
         n = oracle.problem_size(U, mod) - 1
         assert_decisions(sb[idx, :n], ref["sbar"], ref["margin"], tol=mtol)
+
+
+def test_mixed_concurrent_from_two_host_threads(gpu_lib, mixed_case):
+    """Two host threads call the concurrent form at the same time, each on its
+    own stream: they share the library's side streams and events (the
+    enqueue is serialised), and every call gives the sequential result."""
+    import threading
+
+    import torch
+    d, _ = mixed_case
+    V = len(d["cls"])
+    desc = gpu_lib.make_desc(V, 1, 1, 2, prec=1, t_max=10, alpha=0.5)
+    ins = _inputs(d)
+    base = gpu_lib.run_mixed(desc, *ins, want_margin=True)
+    base = {k: v.clone() for k, v in base.items()}
+    torch.cuda.synchronize()
+    results, errors = [[], []], []
+
+    def worker(slot):
+        try:
+            stream = torch.cuda.Stream()
+            ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+            with torch.cuda.stream(stream):
+                for _ in range(4):
+                    r = gpu_lib.run_mixed(desc, *ins, want_margin=True, concurrent=True, ws=ws)
+                    results[slot].append({k: v.clone() for k, v in r.items()})
+            stream.synchronize()
+        except Exception as e:   # surfaced by the assertion below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for slot in range(2):
+        assert len(results[slot]) == 4
+        for r in results[slot]:
+            for k in ("sbar", "margin", "status"):
+                assert torch.equal(r[k], base[k]), (slot, k)
