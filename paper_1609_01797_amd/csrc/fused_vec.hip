@@ -939,6 +939,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   __shared__ float Tr[NMAX * NMAX];
   __shared__ float Dl[N1 + 1];
   __shared__ float al[spectral::kLanczosMax], be2[spectral::kLanczosMax];
+  __shared__ float lz[spectral::lanczos_scratch_floats(NMAX)];
   const int lane = threadIdx.x;
   const long long v = blockIdx.x;
   const int N = a.N, Nm1 = N - 1;
@@ -979,7 +980,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   }
   for (int k = lane; k < N; k += 64) a.D[v * N + k] = Dl[k < Nm1 ? k : N1];
   __syncthreads();
-  const float lam = spectral::lanczos_norm(Tr, N, a.U <= a.B, Q, al, be2);
+  const float lam = spectral::lanczos_norm(Tr, N, a.U <= a.B, jed, Q, al, be2, lz);
   if (lane == 0) {
     a.lam[v] = lam;
     if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);

@@ -32,6 +32,17 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// Sum over the four lanes n, n + 16, n + 32, n + 48 (the same position in the
+// four 16-lane rows), by the two gfx950 lane swaps alone.
+__device__ __forceinline__ float rows_sum(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  v = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  const unsigned w = __float_as_uint(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // Hardware reciprocal, square root and reciprocal square root (about one
 // ulp; the correctly rounded library forms cost some twenty instructions).
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -85,14 +96,25 @@ __device__ inline float start_entry(int i) {
   return 1.0f + (float)(h & 0xFFFFu) * (1.0f / 65536.0f);
 }
 
+// LDS floats lanczos_norm needs beside the basis: w (N) and the
+// coefficients of one reorthogonalisation pass.
+__host__ __device__ constexpr int lanczos_scratch_floats(int n) { return n + 32; }
+
 // ||T~||_2 (largest |eigenvalue|) of the symmetric N x N matrix T, row-major
-// in LDS, by Lanczos with full reorthogonalisation (two passes of modified
-// Gram-Schmidt against every basis vector: each coefficient is removed
-// before the next is taken) and a multisection of the Ritz tridiagonal.  Run by all 64
-// lanes of one wave (N <= 3 * 64); Q: LDS scratch of kLanczosMax * N floats,
-// al / be2: LDS arrays of kLanczosMax floats.  Every lane returns the value.
-__device__ inline float lanczos_norm(const float* T, int N, bool well_posed, float* Q, float* al,
-                                     float* be2) {
+// in LDS, by Lanczos with full reorthogonalisation and a multisection of the
+// Ritz tridiagonal.  The reorthogonalisation is classical Gram-Schmidt taken
+// twice: each pass forms all coefficients q_i . w at once (four lanes per
+// coefficient, one quarter of the rows each, met by two lane swaps) and then
+// subtracts them together, so a pass waits on one reduction instead of one
+// per basis vector.  Run by all 64 lanes of one wave (N <= 3 * 64); Q: LDS
+// scratch of kLanczosMax * N floats, al / be2: LDS arrays of kLanczosMax
+// floats, S: LDS scratch of lanczos_scratch_floats(N) floats.  T~ is
+// semidefinite (coherent detection: T = A^T A; joint detection: T = -A^T A),
+// so ||T~||_2 is its largest eigenvalue, or with nsd the magnitude of its
+// smallest, and only that end of the spectrum is located.  Every lane
+// returns the value.
+__device__ inline float lanczos_norm(const float* T, int N, bool well_posed, bool nsd, float* Q,
+                                     float* al, float* be2, float* S) {
   const int lane = threadIdx.x & (kWave - 1);
   const int m_lim = well_posed ? kLanczosWellPosed : kLanczosMax;
   const int m_cap = N < m_lim ? N : m_lim;
@@ -151,15 +173,45 @@ __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, flo
     m = j + 1;
     scale = fmaxf(scale, fabsf(alpha_j));
     if (j == m_cap - 1) break;
-    // two passes of modified Gram-Schmidt against every Lanczos vector
+    // two passes of classical Gram-Schmidt against every Lanczos vector
+    float* W = S;
+    float* C = S + N;
+    const int slice = lane >> 4;                  // quarter of the rows
+    const int len = (N + 3) >> 2;
+    const int r0 = slice * len, r1 = r0 + len < N ? r0 + len : N;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i <= j; ++i) {
-        const float* qi = Q + (size_t)i * N;
-        float c = 0.f;
-        for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) c += w[s] * qi[r]; }
-        c = wave_sum(c);
-        for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) w[s] -= c * qi[r]; }
+      for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) W[r] = w[s]; }
+      __builtin_amdgcn_wave_barrier();
+      for (int base = 0; base <= j; base += 16) {
+        const int i = base + (lane & 15);
+        float p0 = 0.f, p1 = 0.f;
+        if (i <= j) {
+          const float* qi = Q + (size_t)i * N;
+          int r = r0;
+          for (; r + 2 <= r1; r += 2) {
+            p0 = fmaf(qi[r], W[r], p0);
+            p1 = fmaf(qi[r + 1], W[r + 1], p1);
+          }
+          if (r < r1) p0 = fmaf(qi[r], W[r], p0);
+        }
+        const float c = rows_sum(p0 + p1);
+        if (slice == 0 && i <= j) C[i] = c;
       }
+      __builtin_amdgcn_wave_barrier();
+      for (int s = 0; s < 3; ++s) {
+        const int r = lane + s * kWave;
+        if (r < N) {
+          float a0 = 0.f, a1 = 0.f;
+          int i = 0;
+          for (; i + 2 <= j + 1; i += 2) {
+            a0 = fmaf(C[i], Q[(size_t)i * N + r], a0);
+            a1 = fmaf(C[i + 1], Q[(size_t)(i + 1) * N + r], a1);
+          }
+          if (i <= j) a0 = fmaf(C[i], Q[(size_t)i * N + r], a0);
+          w[s] -= a0 + a1;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
     float bb = 0.f;
     for (int s = 0; s < 3; ++s) { const int r = lane + s * kWave; if (r < N) bb += w[s] * w[s]; }
@@ -182,9 +234,7 @@ __device__ inline float lanczos_norm(const float* T, int N, bool well_posed, flo
     hi = fmaxf(hi, al[i] + r);
   }
   const float pivmin = 1e-30f + 1e-12f * fmaxf(fabsf(lo), fabsf(hi));
-  const float emax = tridiag_extreme(al, be2, m, lo, hi, true, pivmin);
-  const float emin = tridiag_extreme(al, be2, m, lo, hi, false, pivmin);
-  return fmaxf(fabsf(emax), fabsf(emin));
+  return fabsf(tridiag_extreme(al, be2, m, lo, hi, !nsd, pivmin));
 }
 
 }  // namespace spectral

@@ -19,6 +19,13 @@ using spectral::wave_sum;
 constexpr int kBuildThreads = 256;
 constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
+// build_T_kernel's static LDS (two flags, the Lanczos tridiagonal and the
+// reorthogonalisation scratch) is taken from the budget of its dynamic LDS
+constexpr int kBuildStaticLds = 1024;
+static_assert(2 * sizeof(int) + 2 * spectral::kLanczosMax * sizeof(float) +
+                      spectral::lanczos_scratch_floats(TASER_MAX_N) * sizeof(float) <=
+                  (size_t)kBuildStaticLds,
+              "static LDS of build_T_kernel exceeds its reserve");
 
 // One workgroup per vector.
 //   phase 1: complex Gram G = H^H H, b = H^H y, ||y||^2 (JED: H := Y_r,
@@ -136,9 +143,10 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   // ---- ||T~||_2 (first wave only) ----
   float* Q = reinterpret_cast<float*>(smem);            // reuses the channel copy: [m][N]
   __shared__ float al[kLanczosMax], be2[kLanczosMax];
+  __shared__ float lz[spectral::lanczos_scratch_floats(TASER_MAX_N)];
   if (tid < kWave) {
     const int lane = tid;
-    const float lam = spectral::lanczos_norm(T, N, U <= B, Q, al, be2);
+    const float lam = spectral::lanczos_norm(T, N, U <= B, jed, Q, al, be2, lz);
     if (lane == 0) {
       a.lam[v] = lam;
       if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);
@@ -252,7 +260,7 @@ size_t build_T_lds_bytes(int B, int U, int N) {
   size_t q = (size_t)kLanczosMax * N * sizeof(float);
   size_t first = hbytes > q ? hbytes : q;
   const size_t total = first + (size_t)N * N * sizeof(float) + (size_t)N * sizeof(float);
-  return total <= (size_t)kLdsMax ? total : 0;
+  return total <= (size_t)(kLdsMax - kBuildStaticLds) ? total : 0;
 }
 
 size_t solve_lds_bytes(int N) { return 3 * (size_t)(N * (N + 1) / 2) * sizeof(float); }
