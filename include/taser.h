@@ -260,7 +260,7 @@ taser_status_t taser_jed_channel(const taser_desc_t* desc, const void* Y, const 
                                  const int8_t* sbar, void* h, void* stream);
 
 /* Device workspace (bytes) that taser_run needs for this descriptor, written
-   to *bytes: 5,888 bytes per 16 vectors on the group path, 0 on the
+   to *bytes: 4,352 bytes per 16 vectors on the group path, 0 on the
    per-vector path.  Host-only; returns the same errors as taser_run would
    for the descriptor (TASER_ERR_UNSUPPORTED for a shape neither path
    covers). */
@@ -296,7 +296,7 @@ taser_status_t taser_run(const taser_desc_t* desc, const void* H, const void* y,
    device memory (code under HIP graph capture, tight serving loops,
    harnesses that forbid allocation).  The group path keeps its per-group
    state in a device array inside the library (TASER_STATIC_MAX_VECTORS
-   vectors, 23 MiB, held on each device the library runs on until the
+   vectors, 17 MiB, held on each device the library runs on until the
    process ends); the per-vector path needs no state.  Same arguments,
    kernels and results as taser_run.  The call allocates and frees nothing.
    Calls on one device share that array: calls that overlap on one device

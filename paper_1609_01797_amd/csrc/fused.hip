@@ -175,12 +175,15 @@ __device__ __forceinline__ float tridiag_top(const float (&al)[M], const float (
 
 // Workspace per channel group (floats): the MFMA A operands of G~ (its real
 // and imaginary parts R and M; the real form [[R, -M], [M, R]] is rebuilt in
-// registers), the border c~, the column scales D and per-lane D_NN, tau and
-// flags, stored register-major ([register][lane]) so both kernels move them
-// coalesced.
-constexpr int kWsR = 0, kWsM = 256, kWsC = 512, kWsD = 1024, kWsDN = 1280, kWsTau = 1344,
-              kWsFlag = 1408;
-constexpr int kWsFloats = 1472;
+// registers) and the border c~, stored register-major ([register][lane]) so
+// both kernels move them coalesced; then the 16 column scales D (column
+// quad g and register r: entry 4 r + g), and D_NN, tau and flags per vector
+// (entry n).  The state does not depend on the product precision, so one
+// preparation can feed solves of every precision.
+constexpr int kWsR = 0, kWsM = 256, kWsC = 512, kWsD = 1024, kWsDN = 1040, kWsTau = 1056,
+              kWsFlag = 1072;
+constexpr int kWsFloats = 1088;
+static_assert(kWsFloats * sizeof(float) == kGroupWsBytes, "group workspace size");
 
 // Waves (channel groups) per workgroup of the preparation kernel.  Its
 // waves need few registers, so five would fit on a SIMD; four-wave
@@ -430,11 +433,16 @@ __device__ __forceinline__ void prep_finish(const FusedArgs& a, long long grp, b
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) ws[kWsC + (mt * 4 + r) * 64 + lane] = ct[mt][r];
+  // D depends on the column only, D_NN, tau and the flags on the vector only
+  if (n == 0) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) ws[kWsD + r * 64 + lane] = Dc[r];
-  ws[kWsDN + lane] = DN;
-  ws[kWsTau + lane] = tau;
-  ws[kWsFlag + lane] = __int_as_float((nonfinite ? 2 : 0) | (degenerate ? 1 : 0));
+    for (int r = 0; r < 4; ++r) ws[kWsD + 4 * r + g] = Dc[r];
+  }
+  if (g == 0) {
+    ws[kWsDN + n] = DN;
+    ws[kWsTau + n] = tau;
+    ws[kWsFlag + n] = __int_as_float((nonfinite ? 2 : 0) | (degenerate ? 1 : 0));
+  }
   if (g == 0 && a.status)
     a.status[v] = nonfinite ? TASER_VEC_NONFINITE : (degenerate ? TASER_VEC_DEGENERATE : 0);
 }
@@ -544,6 +552,7 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
   const int g = lane >> 4;
   const long long v = (long long)blockIdx.x * 16 + n;
   const float* ws = a.ws + (long long)blockIdx.x * kWsFloats;
+  constexpr bool k16 = P != TASER_PREC_F32;
   float A[2][2][4], ct[2][4], Dc[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -558,10 +567,10 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) ct[mt][r] = ws[kWsC + (mt * 4 + r) * 64 + lane];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) Dc[r] = ws[kWsD + r * 64 + lane];
-  const float DN = ws[kWsDN + lane];
-  const float tau = ws[kWsTau + lane];
-  const int fl = __float_as_int(ws[kWsFlag + lane]);
+  for (int r = 0; r < 4; ++r) Dc[r] = ws[kWsD + 4 * r + g];
+  const float DN = ws[kWsDN + n];
+  const float tau = ws[kWsTau + n];
+  const int fl = __float_as_int(ws[kWsFlag + n]);
   const bool nonfinite = (fl & 2) != 0;
   const bool skip = fl != 0;
   const float m2tau = -2.f * tau;
@@ -572,7 +581,6 @@ __global__ __launch_bounds__(64) void solve_group_qpsk16(FusedArgs a) {
   float mdiag[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) mdiag[d] = g <= d ? m2tau : 0.f;
-  constexpr bool k16 = P != TASER_PREC_F32;
   // float32 path: [V0; V1] = [R -M; M R] [a; b] is the complex product
   // (R + jM)(a + jb), formed with three real products (Gauss):
   // P1 = R a, P2 = M b, P3 = (R + M)(a + b); V0 = P1 - P2, V1 = P3 - P1 - P2.

@@ -9,10 +9,10 @@
 namespace taser {
 namespace {
 
-// 5,888 bytes of state per group of 16 vectors, for up to
-// TASER_STATIC_MAX_VECTORS vectors: 23 MiB.  Every device the library runs
+// 4,352 bytes of state per group of 16 vectors, for up to
+// TASER_STATIC_MAX_VECTORS vectors: 17 MiB.  Every device the library runs
 // on holds its own copy until the process ends.
-constexpr size_t kScratchBytes = (size_t)(TASER_STATIC_MAX_VECTORS / 16) * 5888;
+constexpr size_t kScratchBytes = (size_t)(TASER_STATIC_MAX_VECTORS / 16) * kGroupWsBytes;
 __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr int kMaxDevices = 64;

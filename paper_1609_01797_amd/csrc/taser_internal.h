@@ -61,6 +61,8 @@ hipError_t static_scratch(void** ptr);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_prep(const FusedArgs& a, hipStream_t s);
 hipError_t launch_fused_solve(const FusedArgs& a, hipStream_t s);
+// Bytes of preparation-to-solve state per channel group of 16 vectors.
+constexpr size_t kGroupWsBytes = 4352;
 hipError_t launch_fused_tau(const FusedArgs& a, float* tau, hipStream_t s);
 int calib_elements();
 hipError_t launch_jed_channel(int V, int B, int K, bool qpsk, const void* Y, const void* s0,

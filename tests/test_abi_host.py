@@ -99,7 +99,7 @@ def test_workspace_size_query():
     n = ctypes.c_size_t(0)
     d = taser.make_desc(65536, 128, 16, taser.QPSK, y_per_H=16)
     assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
-    assert n.value == 4096 * 1472 * 4      # 1,472 floats of state per group of 16 vectors
+    assert n.value == 4096 * 1088 * 4      # 1,088 floats of state per group of 16 vectors
     assert lib.taser_workspace_size(ctypes.byref(d), None) == taser.ERR_ARG
     other = taser.make_desc(64, 32, 8, taser.QPSK)      # per-vector kernel: no workspace
     assert lib.taser_workspace_size(ctypes.byref(other), ctypes.byref(n)) == taser.OK and n.value == 0
@@ -110,9 +110,9 @@ def test_workspace_size_query():
     one = ctypes.c_void_p(16)   # non-null but never dereferenced: the call fails first
     assert lib.taser_run(ctypes.byref(d), one, one, z, z, one, z, one, z, z, 0, z) == taser.ERR_WORKSPACE
     # step-size readout: tau pointer and workspace checked before any launch
-    assert lib.taser_run_tau(ctypes.byref(d), one, 4096 * 1472 * 4, z, z) == taser.ERR_ARG
+    assert lib.taser_run_tau(ctypes.byref(d), one, 4096 * 1088 * 4, z, z) == taser.ERR_ARG
     assert lib.taser_run_tau(ctypes.byref(d), one, 16, one, z) == taser.ERR_WORKSPACE
-    assert lib.taser_run_tau(ctypes.byref(d), z, 4096 * 1472 * 4, one, z) == taser.ERR_WORKSPACE
+    assert lib.taser_run_tau(ctypes.byref(d), z, 4096 * 1088 * 4, one, z) == taser.ERR_WORKSPACE
     assert lib.taser_run_tau(ctypes.byref(other), one, 1 << 20, one, z) == taser.ERR_UNSUPPORTED
 
 
@@ -304,7 +304,7 @@ def test_workspace_size_per_vector_descriptors():
         assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK and n.value == 0
     d = taser.make_desc(48, 40, 16, taser.QPSK, y_per_H=16)
     assert lib.taser_workspace_size(ctypes.byref(d), ctypes.byref(n)) == taser.OK
-    assert n.value == 3 * 1472 * 4
+    assert n.value == 3 * 1088 * 4
 
 
 def test_fixed_point_entry_points_reject_before_any_launch():
