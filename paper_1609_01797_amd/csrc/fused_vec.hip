@@ -168,13 +168,6 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-constexpr int kLanczos = 12;
-// Joint estimation and detection: T~ has one dominant eigenvalue (the
-// rank-one signal part of the received block), and six steps reach the
-// float32 resolution of ||T~||_2 from -2 dB up; later steps only add ghost
-// copies.  The remaining entries are parked like a breakdown.
-constexpr int kLanczosJed = 6;
-
 // Largest eigenvalue of the symmetric tridiagonal (al, b2 = beta^2), the same
 // in every lane, by 65-way multisection: in each round lane l tests the
 // point lo + (l + 1)(hi - lo)/65 with a Sturm count (the number of
@@ -214,6 +207,43 @@ __device__ __forceinline__ float top_eigenvalue(const float* al, const float* b2
     if (!(hi - lo > 0.f)) break;
   }
   return 0.5f * (lo + hi);
+}
+
+// The same, for a tridiagonal held one entry per lane (lane k: al_k, b2_k;
+// lanes past the last step hold -1e30 and 0, which count like a breakdown):
+// the M leading entries are read into scalars.
+template <int M>
+__device__ __forceinline__ float top_eigenvalue_lanes(float alv, float b2v) {
+  float al[M], b2[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    al[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(alv), k));
+    b2[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2v), k));
+  }
+  return top_eigenvalue<M>(al, b2);
+}
+
+// Most Lanczos steps a problem of NT tiles takes (the kernels serve U <= 32,
+// so real problems stop at N = 33), and the top eigenvalue of m <= that
+// many entries.
+template <int NT>
+constexpr int kVecLanczosCap =
+    spectral::lanczos_steps(16 * NT + 1 < 33 ? 16 * NT + 1 : 33, false) >
+            spectral::lanczos_steps(16 * NT + 1, true)
+        ? spectral::lanczos_steps(16 * NT + 1 < 33 ? 16 * NT + 1 : 33, false)
+        : spectral::lanczos_steps(16 * NT + 1, true);
+
+template <int NT>
+__device__ __forceinline__ float ritz_top(float alv, float b2v, int m) {
+  static_assert(kVecLanczosCap<NT> <= 24, "Ritz entries beyond the multisections");
+  if (m <= 8) return top_eigenvalue_lanes<8>(alv, b2v);
+  if (m <= 16) return top_eigenvalue_lanes<16>(alv, b2v);
+  return top_eigenvalue_lanes<24>(alv, b2v);
+}
+
+// A value that is the same in every lane, as a scalar.
+__device__ __forceinline__ float uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
 // The padded T is symmetric: its lower triangle is kept packed by rows
@@ -514,14 +544,18 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     const int jr = 4 * (n & 3) + (n >> 2);
     sfor<0, NT>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
-      float part = 0.f;
+      // two partial sums halve the dependent FMA chain
+      float p0 = 0.f, p1 = 0.f;
       sfor<0, NT>([&](auto kc) {
         constexpr int KT = decltype(kc)::value;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) part = fmaf(A[JT][KT][s], x[KT][s], part);
+        p0 = fmaf(A[JT][KT][0], x[KT][0], p0);
+        p1 = fmaf(A[JT][KT][1], x[KT][1], p1);
+        p0 = fmaf(A[JT][KT][2], x[KT][2], p0);
+        p1 = fmaf(A[JT][KT][3], x[KT][3], p1);
       });
-      part = sum_quads(part);
-      if (g == 0) sh[16 * JT + jr] = part;
+      // the four lanes of a quad hold the same sum and store it to the same
+      // word (no lane mask between the rows)
+      sh[16 * JT + jr] = sum_quads(p0 + p1);
     });
     // one wave: its LDS accesses complete in program order; the barrier keeps
     // the compiler from moving them across
@@ -534,13 +568,15 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     __builtin_amdgcn_wave_barrier();
   };
   auto dot = [&](const float (&x)[NT][4], const float (&y)[NT][4]) {
-    float s = 0.f;
+    float s0 = 0.f, s1 = 0.f;
     sfor<0, NT>([&](auto jc) {
       constexpr int JT = decltype(jc)::value;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s = fmaf(x[JT][r], y[JT][r], s);
+      s0 = fmaf(x[JT][0], y[JT][0], s0);
+      s1 = fmaf(x[JT][1], y[JT][1], s1);
+      s0 = fmaf(x[JT][2], y[JT][2], s0);
+      s1 = fmaf(x[JT][3], y[JT][3], s1);
     });
-    return sum_quads(s);
+    return sum_quads(s0 + s1);
   };
 
   // ---------------- step size tau = alpha / ||T~||_2 ----------------
@@ -549,7 +585,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     tau = a.tau_in[v];
   } else {
     // Lanczos on sg*T~ (positive semidefinite in both modes) from T~ e_N.
-    float al[kLanczos], b2[kLanczos];
+    // Lane J keeps alpha_J and beta_J^2 of step J.
+    float alv = -1e30f, b2v = 0.f;
     float Q[NT][4], Qp[NT][4], Wv[NT][4];
     float q32 = sg * tNN, qp32 = 0.f, beta = 0.f;
     sfor<0, NT>([&](auto jc) {
@@ -565,16 +602,12 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       for (int r = 0; r < 4; ++r) Q[JT][r] *= inv0;
     });
     q32 *= inv0;
-    bool done = false;
     float scale = 0.f;
-    const int steps = jed ? kLanczosJed : kLanczos;
-    sfor<0, kLanczos>([&](auto jc) {
-      constexpr int J = decltype(jc)::value;
-      if (J >= steps) {
-        al[J] = -1e30f;
-        b2[J] = 0.f;
-        return;
-      }
+    // spectral::lanczos_steps: joint detection's T~ is the same kind of
+    // matrix (the preconditioned Gram of the block with the pilot column),
+    // and at low SNR its top eigenvalue is as slow to emerge
+    const int steps = spectral::lanczos_steps(job.N, qpsk);
+    for (int J = 0; J < steps; ++J) {
       gemv(Q, Wv);
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;
@@ -582,7 +615,7 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
         for (int r = 0; r < 4; ++r) Wv[JT][r] = sg * (Wv[JT][r] + ct[JT][r] * q32);
       });
       float w32 = sg * (dot(ct, Q) + tNN * q32);
-      const float alj = dot(Wv, Q) + w32 * q32;
+      const float alj = uniform(dot(Wv, Q) + w32 * q32);
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;
 #pragma unroll
@@ -590,17 +623,12 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
           Wv[JT][r] = fmaf(-alj, Q[JT][r], fmaf(-beta, Qp[JT][r], Wv[JT][r]));
       });
       w32 = fmaf(-alj, q32, fmaf(-beta, qp32, w32));
-      const float bb = dot(Wv, Wv) + w32 * w32;
-      if (!done) {
-        al[J] = alj;
-        b2[J] = bb;
-        scale = fmaxf(scale, fabsf(alj));
-        if (!(bb > 1e-12f * scale * scale)) { done = true; b2[J] = 0.f; }
-      } else {
-        al[J] = -1e30f;
-        b2[J] = 0.f;
-      }
-      const float ib = bb > 0.f ? rsq(bb) : 0.f;
+      const float bb = uniform(dot(Wv, Wv) + w32 * w32);
+      scale = fmaxf(scale, fabsf(alj));
+      const bool breakdown = !(bb > 1e-12f * scale * scale);
+      if (lane == J) { alv = alj; b2v = breakdown ? 0.f : bb; }
+      if (breakdown) break;          // the later entries stay parked
+      const float ib = rsq(bb);
       beta = bb * ib;                 // sqrt(bb)
       sfor<0, NT>([&](auto tc) {
         constexpr int JT = decltype(tc)::value;
@@ -609,9 +637,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       });
       qp32 = q32;
       q32 = w32 * ib;
-    });
-    // the tridiagonal of the steps taken (JED: the leading 6 x 6 block)
-    const float lam = jed ? top_eigenvalue<kLanczosJed>(al, b2) : top_eigenvalue<kLanczos>(al, b2);
+    }
+    const float lam = ritz_top<NT>(alv, b2v, steps);
     tau = a.alpha / (lam > 0.f ? lam : 1.f);
   }
   const float m2tau = -2.f * tau;
@@ -931,14 +958,15 @@ template <int NT>
 __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   constexpr int N1 = 16 * NT;
   constexpr int NMAX = N1 + 1;
-  constexpr int kQ = spectral::kLanczosMax * NMAX;
+  constexpr int kSteps = spectral::lanczos_steps(NMAX, false);
+  constexpr int kQ = kSteps * NMAX;
   // the packed T is dead once T~ is in Tr, and the Lanczos basis reuses it
   __shared__ __align__(16) float TQ[VecLds<NT>::TT > kQ ? VecLds<NT>::TT : kQ];
   float* T = TQ;
   float* Q = TQ;
   __shared__ float Tr[NMAX * NMAX];
   __shared__ float Dl[N1 + 1];
-  __shared__ float al[spectral::kLanczosMax], be2[spectral::kLanczosMax];
+  __shared__ float al[kSteps], be2[kSteps];
   __shared__ float lz[spectral::lanczos_scratch_floats(NMAX)];
   const int lane = threadIdx.x;
   const long long v = blockIdx.x;
@@ -980,7 +1008,7 @@ __global__ __launch_bounds__(64) void build_T_vec(StagedArgs a) {
   }
   for (int k = lane; k < N; k += 64) a.D[v * N + k] = Dl[k < Nm1 ? k : N1];
   __syncthreads();
-  const float lam = spectral::lanczos_norm(Tr, N, a.U <= a.B, jed, Q, al, be2, lz);
+  const float lam = spectral::lanczos_norm(Tr, N, a.mod == TASER_QPSK, jed, Q, al, be2, lz);
   if (lane == 0) {
     a.lam[v] = lam;
     if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);

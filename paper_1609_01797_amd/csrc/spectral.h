@@ -7,11 +7,22 @@
 namespace taser {
 namespace spectral {
 
-// Krylov dimension cap for ||T~||_2: 16 steps when U <= B (the top
-// eigenvalue stands out; float32 resolution from -4 dB up), 24 for
-// overloaded systems (U > B), whose leading eigenvalues crowd together.
-constexpr int kLanczosMax = 24;
-constexpr int kLanczosWellPosed = 16;
+// Lanczos steps for ||T~||_2 to float32 resolution, from the start T~ e_N
+// (alone, or with the small unstructured part that lanczos_norm adds).
+// In the real form of a complex problem (QPSK) T~ borders a matrix whose
+// eigenvalues come in pairs, and the Krylov space of T~ e_N stays in an
+// invariant subspace of dimension (N + 1) / 2, so it needs about half the
+// steps of a real problem (BPSK) of the same N.  The worst vector over B/U
+// from 1/2 to 8 and SNR from -4 to 12 dB reached 1e-6 after 9, 15, 17, 20,
+// 25, 27 and 30 steps for BPSK at N = 9, 17, 33, 49, 65, 97 and 129, and
+// after 13, 12, 14, 16, 21 and 21 for QPSK at N = 17, 33, 49, 65, 97 and
+// 129; the rule leaves a margin of three steps or more over those.
+__host__ __device__ constexpr int lanczos_steps(int n, bool paired) {
+  const int m = paired ? 12 + n / 8 : 16 + n / 4;
+  return m < n ? m : n;
+}
+// the most steps any problem size of the library takes
+constexpr int kLanczosMax = lanczos_steps(TASER_MAX_N, false);
 
 // Sum over the 64 lanes of a wave, on the vector ALUs: rotations inside each
 // 16-lane row (DPP row_ror 8, 4, 2, 1), then the gfx950 lane swaps across
@@ -97,8 +108,8 @@ __device__ inline float start_entry(int i) {
 }
 
 // LDS floats lanczos_norm needs beside the basis: w (N) and the
-// coefficients of one reorthogonalisation pass.
-__host__ __device__ constexpr int lanczos_scratch_floats(int n) { return n + 32; }
+// coefficients of one reorthogonalisation pass (one per basis vector).
+__host__ __device__ constexpr int lanczos_scratch_floats(int n) { return n + kLanczosMax; }
 
 // ||T~||_2 (largest |eigenvalue|) of the symmetric N x N matrix T, row-major
 // in LDS, by Lanczos with full reorthogonalisation and a multisection of the
@@ -106,18 +117,18 @@ __host__ __device__ constexpr int lanczos_scratch_floats(int n) { return n + 32;
 // twice: each pass forms all coefficients q_i . w at once (four lanes per
 // coefficient, one quarter of the rows each, met by two lane swaps) and then
 // subtracts them together, so a pass waits on one reduction instead of one
-// per basis vector.  Run by all 64 lanes of one wave (N <= 3 * 64); Q: LDS
-// scratch of kLanczosMax * N floats, al / be2: LDS arrays of kLanczosMax
-// floats, S: LDS scratch of lanczos_scratch_floats(N) floats.  T~ is
+// per basis vector.  Run by all 64 lanes of one wave (N <= 3 * 64); it takes
+// lanczos_steps(N, paired) steps (paired: the real form of a complex
+// problem); Q: LDS scratch of that many times N floats, al / be2: LDS arrays
+// of as many floats, S: LDS scratch of lanczos_scratch_floats(N) floats.  T~ is
 // semidefinite (coherent detection: T = A^T A; joint detection: T = -A^T A),
 // so ||T~||_2 is its largest eigenvalue, or with nsd the magnitude of its
 // smallest, and only that end of the spectrum is located.  Every lane
 // returns the value.
-__device__ inline float lanczos_norm(const float* T, int N, bool well_posed, bool nsd, float* Q,
+__device__ inline float lanczos_norm(const float* T, int N, bool paired, bool nsd, float* Q,
                                      float* al, float* be2, float* S) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int m_lim = well_posed ? kLanczosWellPosed : kLanczosMax;
-  const int m_cap = N < m_lim ? N : m_lim;
+  const int m_cap = lanczos_steps(N, paired);
   // Start: the last column of T~ (the dominant eigenvector weighs the last
   // coordinate heavily, so few steps reach float32 resolution) plus 1 % of
   // a vector without structural zeros, so that an eigenvector orthogonal

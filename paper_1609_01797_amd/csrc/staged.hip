@@ -21,7 +21,7 @@ constexpr int kLdsHBudget = 98304;   // bytes of LDS for the staged channel copy
 constexpr int kLdsMax = 163840;      // LDS per workgroup on gfx950
 // build_T_kernel's static LDS (two flags, the Lanczos tridiagonal and the
 // reorthogonalisation scratch) is taken from the budget of its dynamic LDS
-constexpr int kBuildStaticLds = 1024;
+constexpr int kBuildStaticLds = 1280;
 static_assert(2 * sizeof(int) + 2 * spectral::kLanczosMax * sizeof(float) +
                       spectral::lanczos_scratch_floats(TASER_MAX_N) * sizeof(float) <=
                   (size_t)kBuildStaticLds,
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   // different columns at the same row, which would otherwise share a bank
   const int BP = B + 1;
   const size_t hbytes = (size_t)BP * (U + 1) * sizeof(float2);
-  const size_t qbytes = (size_t)kLanczosMax * N * sizeof(float);
+  const size_t qbytes = (size_t)spectral::lanczos_steps(N, false) * N * sizeof(float);
   const size_t region0 = hbytes > qbytes ? hbytes : qbytes;
   float2* Hc = reinterpret_cast<float2*>(smem);        // [U][BP] column-major channel
   float2* yc = Hc + (size_t)U * BP;                     // [B]
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBuildThreads) void build_T_kernel(StagedArgs a) {
   __shared__ float lz[spectral::lanczos_scratch_floats(TASER_MAX_N)];
   if (tid < kWave) {
     const int lane = tid;
-    const float lam = spectral::lanczos_norm(T, N, U <= B, jed, Q, al, be2, lz);
+    const float lam = spectral::lanczos_norm(T, N, qpsk, jed, Q, al, be2, lz);
     if (lane == 0) {
       a.lam[v] = lam;
       if (a.tau_mode == TASER_TAU_SPECTRAL) a.tau[v] = a.alpha / (lam > 0.f ? lam : 1.f);
@@ -257,7 +257,8 @@ __global__ void detect_kernel(int32_t V, int32_t N, const float* __restrict__ L,
 size_t build_T_lds_bytes(int B, int U, int N) {
   const size_t hbytes = (size_t)(B + 1) * (U + 1) * sizeof(float2);
   if (hbytes > (size_t)kLdsHBudget) return 0;
-  size_t q = (size_t)kLanczosMax * N * sizeof(float);
+  // the basis of the longer (real, BPSK) step rule
+  size_t q = (size_t)spectral::lanczos_steps(N, false) * N * sizeof(float);
   size_t first = hbytes > q ? hbytes : q;
   const size_t total = first + (size_t)N * N * sizeof(float) + (size_t)N * sizeof(float);
   return total <= (size_t)(kLdsMax - kBuildStaticLds) ? total : 0;

@@ -53,9 +53,32 @@ def test_vec_coherent(gpu_lib, case):
     assert_L_parity(unpack_lower(g["L"], N), ref["L"])
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
     np.testing.assert_array_equal(g["status"], ref["status"])
-    # tau from the in-kernel Lanczos + Laguerre estimate
+    # tau from the in-kernel Lanczos estimate of the norm
     desc = gpu_lib.make_desc(V, B, U, mod, y_per_H=yph, t_max=t_max, alpha=alpha)
     g = run_fused(gpu_lib, desc, d["H"], d["y"])
+    assert_L_parity(unpack_lower(g["L"], N), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
+# Spectra that need many Lanczos steps: real (BPSK) problems with U near B,
+# whose T~ has N distinct eigenvalues, and QPSK at N = 65.  (B, U, mod, snr)
+HARD_SPECTRA = [(64, 32, oracle.BPSK, 4.0), (32, 32, oracle.BPSK, -4.0), (40, 32, oracle.BPSK, 0.0),
+                (128, 32, oracle.QPSK, -4.0), (64, 32, oracle.QPSK, 4.0), (32, 16, oracle.QPSK, -4.0)]
+
+
+@pytest.mark.parametrize("B, U, mod, snr", HARD_SPECTRA, ids=lambda x: str(x))
+@pytest.mark.parametrize("t_max", [1, 10])
+def test_vec_spectral_hard_spectra(gpu_lib, B, U, mod, snr, t_max):
+    """The per-vector kernel's own step size where the top eigenvalue of T~
+    is slow to emerge (BPSK: 16 + N/4 Lanczos steps, QPSK: 12 + N/8): L~
+    within 1e-5 of the oracle's, which takes ||T~||_2 from LAPACK.  After one
+    iteration L~ moves with tau to first order, so an eigenvalue a few 1e-5
+    short already fails."""
+    d = sim.gen_mimo(B, U, mod, 256, 1, snr, sim.seed_for(3, snr_index=int(snr) + 70, shard=B + U + mod))
+    ref = oracle.detect_coherent(d["H"], d["y"], mod, alpha=0.5, t_max=t_max)
+    desc = gpu_lib.make_desc(256, B, U, mod, t_max=t_max, alpha=0.5)
+    g = run_fused(gpu_lib, desc, d["H"], d["y"])
+    N = oracle.problem_size(U, mod)
     assert_L_parity(unpack_lower(g["L"], N), ref["L"])
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
@@ -64,16 +87,34 @@ JED = [(oracle.QPSK, 16, 16, 600, 20), (oracle.BPSK, 16, 8, 400, 20), (oracle.QP
        (oracle.BPSK, 8, 32, 100, 12), (oracle.QPSK, 24, 30, 50, 10)]
 
 
-@pytest.mark.parametrize("snr", [-2.0, 0.0, 12.0])
-def test_vec_jed_spectral_low_snr(gpu_lib, snr):
-    """Joint detection with the kernel's own step size (six Lanczos steps from
-    T~ e_N) across the SNR range of the JED workload: L~ within 1e-5 of the
-    oracle, which uses LAPACK's ||T~||_2."""
-    d = sim.gen_jed(16, 16, oracle.QPSK, 400, snr, sim.seed_for(5, snr_index=int(snr) + 30))
-    ref = oracle.detect_jed(d["Y"], d["s0"], oracle.QPSK, alpha=0.5, t_max=20)
-    desc = gpu_lib.make_desc(400, 16, 16, oracle.QPSK, mode=gpu_lib.JED, t_max=20, alpha=0.5)
+@pytest.mark.parametrize("mod, snr", [(oracle.QPSK, -10.0), (oracle.QPSK, -4.0), (oracle.QPSK, -2.0),
+                                      (oracle.QPSK, 0.0), (oracle.QPSK, 12.0), (oracle.BPSK, -14.0),
+                                      (oracle.BPSK, -6.0)])
+def test_vec_jed_spectral_low_snr(gpu_lib, mod, snr):
+    """Joint detection with the kernel's own step size over the SNR range of
+    the 16x16 BER sweeps (down to -10 dB QPSK, -14 dB BPSK): there noise
+    dominates T~ and its top eigenvalue emerges as slowly as in coherent
+    detection (12 + N/8 Lanczos steps for QPSK, 16 + N/4 for BPSK).  L~
+    within 1e-5 of the oracle, which uses LAPACK's ||T~||_2."""
+    d = sim.gen_jed(16, 16, mod, 400, snr, sim.seed_for(5, snr_index=int(snr) + 30, shard=mod))
+    ref = oracle.detect_jed(d["Y"], d["s0"], mod, alpha=0.5, t_max=20)
+    desc = gpu_lib.make_desc(400, 16, 16, mod, mode=gpu_lib.JED, t_max=20, alpha=0.5)
     g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"])
-    assert_L_parity(unpack_lower(g["L"], 33), ref["L"])
+    assert_L_parity(unpack_lower(g["L"], oracle.problem_size(16, mod)), ref["L"])
+    assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
+
+
+@pytest.mark.parametrize("snr", [-4.0, 0.0])
+def test_vec_jed_short_blocks(gpu_lib, snr):
+    """Joint detection of BPSK blocks of 16 slots on 4 antennas with the
+    kernel's own step size: T~ (N = 17) has rank at most 8 and its top
+    eigenvalue does not stand out from the rest.  L~ within 1e-5 of the
+    oracle's."""
+    d = sim.gen_jed(4, 16, oracle.BPSK, 300, snr, sim.seed_for(5, snr_index=int(snr) + 80))
+    ref = oracle.detect_jed(d["Y"], d["s0"], oracle.BPSK, alpha=0.5, t_max=10)
+    desc = gpu_lib.make_desc(300, 4, 16, oracle.BPSK, mode=gpu_lib.JED, t_max=10, alpha=0.5)
+    g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"])
+    assert_L_parity(unpack_lower(g["L"], 17), ref["L"])
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
 

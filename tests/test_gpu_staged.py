@@ -36,6 +36,8 @@ COHERENT_CASES = [
     (256, 32, oracle.QPSK, 24, 1, 12.0, 10, 0.5),        # 65
     (12, 5, oracle.QPSK, 77, 1, 4.0, 7, 0.7),            # 11: ragged sizes
     (40, 64, oracle.BPSK, 9, 1, 20.0, 3, 0.4),           # 65: overloaded BPSK
+    (160, 64, oracle.QPSK, 6, 1, 12.0, 10, 0.5),         # 129: the largest N accepted
+    (8, 1, oracle.BPSK, 50, 1, 3.0, 6, 0.5),             # 2: the smallest N
 ]
 
 
@@ -75,12 +77,17 @@ def test_staged_coherent_spectral_tau(gpu_lib, case):
 
 @pytest.mark.parametrize("B, U, mod, snr", [(128, 16, oracle.QPSK, -4.0), (64, 16, oracle.QPSK, 4.0),
                                             (40, 64, oracle.BPSK, 20.0), (40, 64, oracle.BPSK, 0.0),
-                                            (16, 32, oracle.QPSK, 10.0)])
+                                            (16, 32, oracle.QPSK, 10.0), (160, 64, oracle.QPSK, 8.0),
+                                            (96, 64, oracle.QPSK, 0.0), (8, 1, oracle.BPSK, 3.0),
+                                            (64, 32, oracle.BPSK, 4.0), (128, 64, oracle.BPSK, -4.0),
+                                            (80, 64, oracle.BPSK, 0.0), (90, 128, oracle.BPSK, 4.0),
+                                            (64, 128, oracle.BPSK, -4.0)])
 def test_staged_lambda_pin(gpu_lib, B, U, mod, snr):
     """||T~||_2 of the staged build (Lanczos from the last column of T~ with
-    full reorthogonalisation: 16 steps when U <= B, 24 for overloaded
-    systems) against LAPACK's eigvalsh, 1e-5 relative, at low SNR and for
-    overloaded channels."""
+    full reorthogonalisation, 12 + N/8 steps for QPSK and 16 + N/4 for BPSK)
+    against LAPACK's eigvalsh, 1e-5 relative, at low SNR, for overloaded
+    channels, for real problems with U near B (N distinct eigenvalues) and
+    at the largest N."""
     d = sim.gen_mimo(B, U, mod, 256, 1, snr, sim.seed_for(1, snr_index=int(snr) + 20, shard=U))
     T = oracle.build_T_coherent(d["H"], d["y"], mod)
     _, Tt, _ = oracle.precondition(T)
