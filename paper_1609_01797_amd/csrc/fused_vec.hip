@@ -116,6 +116,34 @@ __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
+// Sum over the N1 = 16, 32 or 64 entries of a vector held one entry per lane
+// (lane l holds entry l mod N1), with the same bits in every lane: each level
+// pairs two lanes that add the same two partial sums (lane ^ 1, lane ^ 2,
+// the half-row and row mirrors, then the gfx950 row swaps).  A rotation
+// tree would give every lane its own order of additions, and the copies of
+// the Lanczos vector would drift apart.
+template <int N1>
+__device__ __forceinline__ float sum_lanes(float x) {
+  // x rounded in its register first: a product contracted into the first
+  // addition would be exact in one lane of a pair and rounded in the other
+  asm volatile("" : "+v"(x));
+  x += dpp_f<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_f<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_f<0x141>(x);   // row_half_mirror
+  x += dpp_f<0x140>(x);   // row_mirror
+  if constexpr (N1 >= 64) {
+    const unsigned u = __float_as_uint(x);
+    const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    x = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  }
+  if constexpr (N1 >= 32) {
+    const unsigned u = __float_as_uint(x);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  return x;
+}
+
 // One level of a transpose-reduction inside 16-lane rows: each lane swaps
 // half of its K values with its DPP partner (an involution of the row) and
 // keeps the half that `upper` selects, summed with the partner's copy.
@@ -536,6 +564,10 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       ct[JT][r] = skip ? 0.f : T[tix(N1, j)] * (rcp(Dl[j]) * iDN);
     }
   });
+  // the last column of T~ once more, one entry per lane (lane l: entry
+  // l mod N1), for the step size's Lanczos vectors
+  const int jl = lane & (N1 - 1);
+  const float ctd = skip ? 0.f : T[tix(N1, jl)] * (rcp(Dl[jl]) * iDN);
   __syncthreads();   // T is dead from here on; sh may be reused freely
 
   // w (row layout, index 16 jt + jj(m) in lane (m, p)) = G~ x, with x in
@@ -585,56 +617,71 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     tau = a.tau_in[v];
   } else {
     // Lanczos on sg*T~ (positive semidefinite in both modes) from T~ e_N.
-    // Lane J keeps alpha_J and beta_J^2 of step J.
-    float alv = -1e30f, b2v = 0.f;
-    float Q[NT][4], Qp[NT][4], Wv[NT][4];
-    float q32 = sg * tNN, qp32 = 0.f, beta = 0.f;
-    sfor<0, NT>([&](auto jc) {
-      constexpr int JT = decltype(jc)::value;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) { Q[JT][r] = sg * ct[JT][r]; Qp[JT][r] = 0.f; }
-    });
-    const float nrm = dot(Q, Q) + q32 * q32;
+    // The Lanczos vectors are held one entry per lane (the last entry, index
+    // N1, as a scalar), so updates and inner products take one instruction
+    // per lane; the product with G~ reads the vector in the column layout of
+    // the A registers from LDS (the T region, dead by now) and returns the
+    // row sums through the shuffle buffer.  Lane J keeps alpha_J and
+    // beta_J^2 of step J.
+    float* xs = lds;
+    const int jr = 4 * (n & 3) + (n >> 2);
+    float q = sg * ctd, qp = 0.f, q32 = sg * tNN, qp32 = 0.f, beta = 0.f;
+    const float nrm = sum_lanes<N1>(q * q) + q32 * q32;
     const float inv0 = nrm > 0.f ? rsqrtf(nrm) : 0.f;
-    sfor<0, NT>([&](auto jc) {
-      constexpr int JT = decltype(jc)::value;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Q[JT][r] *= inv0;
-    });
+    q *= inv0;
     q32 *= inv0;
-    float scale = 0.f;
-    // spectral::lanczos_steps: joint detection's T~ is the same kind of
-    // matrix (the preconditioned Gram of the block with the pilot column),
-    // and at low SNR its top eigenvalue is as slow to emerge
-    const int steps = spectral::lanczos_steps(job.N, qpsk);
+    float alv = -1e30f, b2v = 0.f, scale = 0.f;
+    // spectral::lanczos_steps (joint detection's T~ is the same kind of
+    // matrix: the preconditioned Gram of the block with the pilot column),
+    // and never more than the dimension of the Krylov space of T~ e_N: that
+    // vector lies in the range of T~ (rank at most 2B for BPSK, B complex
+    // dimensions for QPSK) and, for QPSK, in the invariant subspace of
+    // dimension (N + 1) / 2 of the paired real form.  Plain float32 Lanczos
+    // does not see that space close (beta stays at 1e-4 to 1e-2 of the scale
+    // instead of vanishing), and steps beyond it can put a spurious Ritz
+    // value above ||T~||_2.
+    const int kdim = qpsk ? min(job.B, (job.N + 1) / 2) : min(2 * job.B, job.N);
+    const int steps = min(spectral::lanczos_steps(job.N, qpsk), kdim);
     for (int J = 0; J < steps; ++J) {
-      gemv(Q, Wv);
-      sfor<0, NT>([&](auto tc) {
-        constexpr int JT = decltype(tc)::value;
+      // w = sg (G~ q + c~ q_N): the copies of an entry store the same word;
+      // one wave's LDS accesses complete in program order, and the barriers
+      // keep the compiler from moving them across
+      xs[jl] = q;
+      __builtin_amdgcn_wave_barrier();
+      float xc[NT][4];
+      sfor<0, NT>([&](auto kc) {
+        constexpr int KT = decltype(kc)::value;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Wv[JT][r] = sg * (Wv[JT][r] + ct[JT][r] * q32);
+        for (int r = 0; r < 4; ++r) xc[KT][r] = xs[16 * KT + 4 * r + g];
       });
-      float w32 = sg * (dot(ct, Q) + tNN * q32);
-      const float alj = uniform(dot(Wv, Q) + w32 * q32);
-      sfor<0, NT>([&](auto tc) {
-        constexpr int JT = decltype(tc)::value;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Wv[JT][r] = fmaf(-alj, Q[JT][r], fmaf(-beta, Qp[JT][r], Wv[JT][r]));
+      sfor<0, NT>([&](auto jc) {
+        constexpr int JT = decltype(jc)::value;
+        float p0 = 0.f, p1 = 0.f;
+        sfor<0, NT>([&](auto kc) {
+          constexpr int KT = decltype(kc)::value;
+          p0 = fmaf(A[JT][KT][0], xc[KT][0], p0);
+          p1 = fmaf(A[JT][KT][1], xc[KT][1], p1);
+          p0 = fmaf(A[JT][KT][2], xc[KT][2], p0);
+          p1 = fmaf(A[JT][KT][3], xc[KT][3], p1);
+        });
+        sh[16 * JT + jr] = sum_quads(p0 + p1);
       });
+      __builtin_amdgcn_wave_barrier();
+      float w = sg * (sh[jl] + ctd * q32);
+      __builtin_amdgcn_wave_barrier();
+      float w32 = sg * (sum_lanes<N1>(ctd * q) + tNN * q32);
+      const float alj = uniform(sum_lanes<N1>(w * q) + w32 * q32);
+      w = fmaf(-alj, q, fmaf(-beta, qp, w));
       w32 = fmaf(-alj, q32, fmaf(-beta, qp32, w32));
-      const float bb = uniform(dot(Wv, Wv) + w32 * w32);
+      const float bb = uniform(sum_lanes<N1>(w * w) + w32 * w32);
       scale = fmaxf(scale, fabsf(alj));
       const bool breakdown = !(bb > 1e-12f * scale * scale);
       if (lane == J) { alv = alj; b2v = breakdown ? 0.f : bb; }
       if (breakdown) break;          // the later entries stay parked
       const float ib = rsq(bb);
       beta = bb * ib;                 // sqrt(bb)
-      sfor<0, NT>([&](auto tc) {
-        constexpr int JT = decltype(tc)::value;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) { Qp[JT][r] = Q[JT][r]; Q[JT][r] = Wv[JT][r] * ib; }
-      });
+      qp = q;
+      q = w * ib;
       qp32 = q32;
       q32 = w32 * ib;
     }
