@@ -564,10 +564,12 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
       ct[JT][r] = skip ? 0.f : T[tix(N1, j)] * (rcp(Dl[j]) * iDN);
     }
   });
-  // the last column of T~ once more, one entry per lane (lane l: entry
-  // l mod N1), for the step size's Lanczos vectors
-  const int jl = lane & (N1 - 1);
-  const float ctd = skip ? 0.f : T[tix(N1, jl)] * (rcp(Dl[jl]) * iDN);
+  // the last column of T~ once more, one entry per lane, for the step
+  // size's Lanczos vectors: lane (n, g) holds entry 16 (g mod NT) + jr(n),
+  // the row that the matrix registers' row sums leave in that lane
+  const int jt_own = g & (NT - 1);
+  const int e_own = 16 * jt_own + 4 * (n & 3) + (n >> 2);
+  const float ctd = skip ? 0.f : T[tix(N1, e_own)] * (rcp(Dl[e_own]) * iDN);
   __syncthreads();   // T is dead from here on; sh may be reused freely
 
   // w (row layout, index 16 jt + jj(m) in lane (m, p)) = G~ x, with x in
@@ -620,11 +622,10 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     // The Lanczos vectors are held one entry per lane (the last entry, index
     // N1, as a scalar), so updates and inner products take one instruction
     // per lane; the product with G~ reads the vector in the column layout of
-    // the A registers from LDS (the T region, dead by now) and returns the
-    // row sums through the shuffle buffer.  Lane J keeps alpha_J and
-    // beta_J^2 of step J.
+    // the A registers from LDS (the T region, dead by now), and each lane
+    // keeps the row sum of its own entry.  Lane J keeps alpha_J and beta_J^2
+    // of step J.
     float* xs = lds;
-    const int jr = 4 * (n & 3) + (n >> 2);
     float q = sg * ctd, qp = 0.f, q32 = sg * tNN, qp32 = 0.f, beta = 0.f;
     const float nrm = sum_lanes<N1>(q * q) + q32 * q32;
     const float inv0 = nrm > 0.f ? rsqrtf(nrm) : 0.f;
@@ -644,9 +645,9 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     const int steps = min(spectral::lanczos_steps(job.N, qpsk), kdim);
     for (int J = 0; J < steps; ++J) {
       // w = sg (G~ q + c~ q_N): the copies of an entry store the same word;
-      // one wave's LDS accesses complete in program order, and the barriers
-      // keep the compiler from moving them across
-      xs[jl] = q;
+      // one wave's LDS accesses complete in program order, and the barrier
+      // keeps the compiler from moving them across
+      xs[e_own] = q;
       __builtin_amdgcn_wave_barrier();
       float xc[NT][4];
       sfor<0, NT>([&](auto kc) {
@@ -654,6 +655,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) xc[KT][r] = xs[16 * KT + 4 * r + g];
       });
+      __builtin_amdgcn_wave_barrier();
+      float rs = 0.f;                 // row 16 jt_own + jr(n) of G~ q
       sfor<0, NT>([&](auto jc) {
         constexpr int JT = decltype(jc)::value;
         float p0 = 0.f, p1 = 0.f;
@@ -664,11 +667,10 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
           p0 = fmaf(A[JT][KT][2], xc[KT][2], p0);
           p1 = fmaf(A[JT][KT][3], xc[KT][3], p1);
         });
-        sh[16 * JT + jr] = sum_quads(p0 + p1);
+        const float row = sum_quads(p0 + p1);
+        rs = jt_own == JT ? row : rs;
       });
-      __builtin_amdgcn_wave_barrier();
-      float w = sg * (sh[jl] + ctd * q32);
-      __builtin_amdgcn_wave_barrier();
+      float w = sg * (rs + ctd * q32);
       float w32 = sg * (sum_lanes<N1>(ctd * q) + tNN * q32);
       const float alj = uniform(sum_lanes<N1>(w * q) + w32 * q32);
       w = fmaf(-alj, q, fmaf(-beta, qp, w));
