@@ -232,7 +232,9 @@ __device__ __forceinline__ float top_eigenvalue(const float* al, const float* b2
     const float nlo = lo + w * (float)first;
     hi = first < 64 ? lo + w * (float)(first + 1) : hi;
     lo = nlo;
-    if (!(hi - lo > 0.f)) break;
+    // a bracket within 1e-7 of the value is below what float32 Lanczos
+    // resolves (about 1e-6); most brackets get there in three or four rounds
+    if (!(hi - lo > 1e-7f * fabsf(hi))) break;
   }
   return 0.5f * (lo + hi);
 }

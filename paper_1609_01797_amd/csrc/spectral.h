@@ -93,7 +93,8 @@ __device__ inline float tridiag_extreme(const float* a, const float* b2, int m, 
     const float new_lo = lo + w * (float)first;
     lo = new_lo;
     hi = new_hi;
-    if (!(hi - lo > 0.f)) break;
+    // a bracket within 1e-7 of the value is below the Lanczos resolution
+    if (!(hi - lo > 1e-7f * fmaxf(fabsf(lo), fabsf(hi)))) break;
   }
   return 0.5f * (lo + hi);
 }
