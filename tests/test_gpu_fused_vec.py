@@ -62,8 +62,11 @@ def test_vec_coherent(gpu_lib, case):
 
 # Spectra that need many Lanczos steps: real (BPSK) problems with U near B,
 # whose T~ has N distinct eigenvalues, and QPSK at N = 65.  (B, U, mod, snr)
+# Also rank-deficient T~ with very few antennas, where the Krylov space of
+# T~ e_N closes after B (QPSK) or 2B (BPSK) steps.
 HARD_SPECTRA = [(64, 32, oracle.BPSK, 4.0), (32, 32, oracle.BPSK, -4.0), (40, 32, oracle.BPSK, 0.0),
-                (128, 32, oracle.QPSK, -4.0), (64, 32, oracle.QPSK, 4.0), (32, 16, oracle.QPSK, -4.0)]
+                (128, 32, oracle.QPSK, -4.0), (64, 32, oracle.QPSK, 4.0), (32, 16, oracle.QPSK, -4.0),
+                (2, 8, oracle.QPSK, 6.0), (3, 16, oracle.BPSK, 6.0), (1, 4, oracle.QPSK, 10.0)]
 
 
 @pytest.mark.parametrize("B, U, mod, snr", HARD_SPECTRA, ids=lambda x: str(x))
