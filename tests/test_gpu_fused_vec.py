@@ -107,17 +107,19 @@ def test_vec_jed_spectral_low_snr(gpu_lib, mod, snr):
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
 
+@pytest.mark.parametrize("mod, Bx", [(oracle.BPSK, 4), (oracle.QPSK, 2), (oracle.QPSK, 4)])
 @pytest.mark.parametrize("snr", [-4.0, 0.0])
-def test_vec_jed_short_blocks(gpu_lib, snr):
-    """Joint detection of BPSK blocks of 16 slots on 4 antennas with the
-    kernel's own step size: T~ (N = 17) has rank at most 8 and its top
-    eigenvalue does not stand out from the rest.  L~ within 1e-5 of the
+def test_vec_jed_short_blocks(gpu_lib, mod, Bx, snr):
+    """Joint detection of blocks of 16 slots on 2 or 4 antennas with the
+    kernel's own step size: T~ has rank at most 2B (BPSK) or B complex
+    dimensions (QPSK), its top eigenvalue does not stand out, and the Krylov
+    space of T~ e_N closes after that many steps.  L~ within 1e-5 of the
     oracle's."""
-    d = sim.gen_jed(4, 16, oracle.BPSK, 300, snr, sim.seed_for(5, snr_index=int(snr) + 80))
-    ref = oracle.detect_jed(d["Y"], d["s0"], oracle.BPSK, alpha=0.5, t_max=10)
-    desc = gpu_lib.make_desc(300, 4, 16, oracle.BPSK, mode=gpu_lib.JED, t_max=10, alpha=0.5)
+    d = sim.gen_jed(Bx, 16, mod, 300, snr, sim.seed_for(5, snr_index=int(snr) + 80, shard=Bx + mod))
+    ref = oracle.detect_jed(d["Y"], d["s0"], mod, alpha=0.5, t_max=10)
+    desc = gpu_lib.make_desc(300, Bx, 16, mod, mode=gpu_lib.JED, t_max=10, alpha=0.5)
     g = run_fused(gpu_lib, desc, y=d["Y"], s0=d["s0"])
-    assert_L_parity(unpack_lower(g["L"], 17), ref["L"])
+    assert_L_parity(unpack_lower(g["L"], oracle.problem_size(16, mod)), ref["L"])
     assert_decisions(g["sbar"], ref["sbar"], ref["margin"])
 
 
