@@ -66,7 +66,8 @@ def test_vec_coherent(gpu_lib, case):
 # T~ e_N closes after B (QPSK) or 2B (BPSK) steps.
 HARD_SPECTRA = [(64, 32, oracle.BPSK, 4.0), (32, 32, oracle.BPSK, -4.0), (40, 32, oracle.BPSK, 0.0),
                 (128, 32, oracle.QPSK, -4.0), (64, 32, oracle.QPSK, 4.0), (32, 16, oracle.QPSK, -4.0),
-                (2, 8, oracle.QPSK, 6.0), (3, 16, oracle.BPSK, 6.0), (1, 4, oracle.QPSK, 10.0)]
+                (2, 8, oracle.QPSK, 6.0), (3, 16, oracle.BPSK, 6.0), (1, 4, oracle.QPSK, 10.0),
+                (8, 1, oracle.BPSK, 3.0), (4, 1, oracle.QPSK, 3.0)]   # N = 2 and 3: two steps
 
 
 @pytest.mark.parametrize("B, U, mod, snr", HARD_SPECTRA, ids=lambda x: str(x))
