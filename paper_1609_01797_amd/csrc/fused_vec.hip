@@ -641,8 +641,8 @@ __device__ __forceinline__ void vec_body(const FusedArgs& a, const VecJob& job, 
     // dimensions for QPSK) and, for QPSK, in the invariant subspace of
     // dimension (N + 1) / 2 of the paired real form.  Plain float32 Lanczos
     // does not see that space close (beta stays at 1e-4 to 1e-2 of the scale
-    // instead of vanishing), and steps beyond it can put a spurious Ritz
-    // value above ||T~||_2.
+    // instead of vanishing), so steps beyond it would only multiply rounding
+    // noise.
     const int kdim = qpsk ? min(job.B, (job.N + 1) / 2) : min(2 * job.B, job.N);
     const int steps = min(spectral::lanczos_steps(job.N, qpsk), kdim);
     for (int J = 0; J < steps; ++J) {
